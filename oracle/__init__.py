@@ -1,0 +1,148 @@
+"""CPU oracle for the 3D FoF and the hierarchical 6D phase-space FoF.
+
+TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers; the product package never
+imports this module.  The arithmetic lives in ``fof_oracle.c`` (plain C,
+single-threaded, fp32 pair arithmetic without contraction, exact integer
+moments); this file only compiles it with gcc and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fof_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-fexcess-precision=standard", "-lm"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (always, when force is set)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS[:-1], _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
+    lib.oracle_fof3d.argtypes = [P, P, P, i64, f32, f32, P]
+    lib.oracle_fof3d_brute.argtypes = [P, P, P, i64, f32, f32, P]
+    lib.oracle_phase_fof.argtypes = [P, P, P, P, P, P, i64, f32, P, i32, i32, f64, i64,
+                                     i64, P, P, P, P, P, P, P, P, P, P, P]
+    lib.oracle_i128_to_f64.argtypes = [i64, ctypes.c_uint64]
+    lib.oracle_i128_to_f64.restype = f64
+    lib.oracle_select_rank.argtypes = [i64, f64]
+    lib.oracle_select_rank.restype = i64
+    lib.oracle_node_nn.argtypes = [P, P, P, P, P, P, f32, P, i64, f32, f32, P]
+    lib.oracle_node_norm.argtypes = [P, P, P, P, P, P, f32, P, i64, P]
+    _lib = lib
+    return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def fof3d(x, y, z, box, link_len, brute=False):
+    """3D FoF labels (smallest member index per group), int32[n]."""
+    lib = _load()
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.size
+    lab = np.empty(n, dtype=np.int32)
+    fn = lib.oracle_fof3d_brute if brute else lib.oracle_fof3d
+    rc = fn(_ptr(x), _ptr(y), _ptr(z), n, float(box), float(link_len), _ptr(lab))
+    if rc != 0:
+        raise OracleError(f"oracle_fof3d failed: {rc}")
+    return lab
+
+
+NODE_FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2")
+
+
+def phase_fof(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=0.7,
+              brute_max=3000):
+    """Hierarchical 6D FoF.  Returns a dict of numpy arrays: the node fields
+    in canonical (level, min_index) order, plus ``deepest`` per particle."""
+    lib = _load()
+    arrs = [_f32(a) for a in (x, y, z, vx, vy, vz)]
+    lab = np.ascontiguousarray(np.asarray(fof_labels, dtype=np.int32))
+    n = arrs[0].size
+    cap = max(64, n // 4)
+    while True:
+        out = dict(level=np.empty(cap, np.int32), min_index=np.empty(cap, np.int32),
+                   parent=np.empty(cap, np.int32), size=np.empty(cap, np.int32),
+                   l2=np.empty(cap, np.float32), a=np.empty(cap, np.float32),
+                   c=np.empty(cap, np.float32), sx2=np.empty(cap, np.float32),
+                   sv2=np.empty(cap, np.float32))
+        deepest = np.empty(n, np.int32)
+        nn = ctypes.c_int64(0)
+        rc = lib.oracle_phase_fof(*[_ptr(a) for a in arrs], n, float(box), _ptr(lab),
+                                  int(min_group), int(min_sub), float(f), int(brute_max),
+                                  cap, *[_ptr(out[k]) for k in NODE_FIELDS],
+                                  _ptr(deepest), ctypes.byref(nn))
+        if rc == -4:
+            cap = int(nn.value) + 16
+            continue
+        if rc != 0:
+            raise OracleError(f"oracle_phase_fof failed: {rc}")
+        m = int(nn.value)
+        res = {k: v[:m].copy() for k, v in out.items()}
+        res["deepest"] = deepest
+        return res
+
+
+def i128_to_f64(v: int) -> float:
+    lib = _load()
+    v &= (1 << 128) - 1
+    hi = v >> 64
+    if hi >= 1 << 63:
+        hi -= 1 << 64
+    return lib.oracle_i128_to_f64(hi, v & ((1 << 64) - 1))
+
+
+def select_rank(n: int, f: float) -> int:
+    return int(_load().oracle_select_rank(int(n), float(f)))
+
+
+def node_nn(x, y, z, vx, vy, vz, box, members, a, c):
+    lib = _load()
+    arrs = [_f32(q) for q in (x, y, z, vx, vy, vz)]
+    mem = np.ascontiguousarray(np.asarray(members, dtype=np.int64))
+    d2 = np.empty(mem.size, np.float32)
+    lib.oracle_node_nn(*[_ptr(q) for q in arrs], float(box), _ptr(mem), mem.size,
+                       float(a), float(c), _ptr(d2))
+    return d2
+
+
+def node_norm(x, y, z, vx, vy, vz, box, members):
+    """(a, c, sx2, sv2) of one member set (members ascending)."""
+    lib = _load()
+    arrs = [_f32(q) for q in (x, y, z, vx, vy, vz)]
+    mem = np.ascontiguousarray(np.sort(np.asarray(members, dtype=np.int64)))
+    out = np.empty(4, np.float32)
+    lib.oracle_node_norm(*[_ptr(q) for q in arrs], float(box), _ptr(mem), mem.size, _ptr(out))
+    return tuple(float(v) for v in out)

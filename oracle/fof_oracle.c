@@ -1,0 +1,696 @@
+/*
+ * fof_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded CPU reference for the two steps the paper
+ * names in its Parallelization section: a 3D friends-of-friends pass over one
+ * process's periodic sub-box, and, inside every FoF halo, subhalo finding in
+ * 6D phase space (Rockstar's hierarchical phase-space FoF, which the paper
+ * cites in its Summary for the method).  Only the test-suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load this library; the product
+ * path never does.  It shares no code with the GPU library.
+ *
+ * The result is a pure function of the particle set:
+ *   3D:  the transitive closure of the pair relation D(i,j) <= ll^2, labels
+ *        equal to the smallest member index of each group.
+ *   6D:  for each 3D group of at least min_group members (a level-0 node):
+ *        dispersions from exact integer moments -> metric factors a, c;
+ *        every member's nearest-neighbour distance d_i^2 under
+ *        d^2 = a*Dx + c*Dv; the node's linking length l^2 = the k-th smallest
+ *        d_i^2 with k = ceil(f n); links d^2(i,j) <= l^2; components of at
+ *        least min_sub members (other than the whole node) become children,
+ *        which are split again.
+ *
+ * Floating-point readings (fixed here, identical on the GPU side):
+ *   dx = fl(xi - xj), then one periodic image shift:
+ *        dx > L/2 -> fl(dx - L);  dx < -L/2 -> fl(dx + L)
+ *   D  = fl( fl( fl(dx*dx) + fl(dy*dy) ) + fl(dz*dz) ), no FMA contraction
+ *   d^2 = fl( fl(a*Dx) + fl(c*Dv) ), Dv as D over velocity differences
+ * Build with -ffp-contract=off -fno-fast-math.
+ *
+ * Acceleration structures (a position cell grid) only restrict which pairs
+ * are evaluated; pruning uses lower bounds with a wide safety margin, and the
+ * brute-force paths (all pairs) are kept and selectable for pinning.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __int128 i128;
+
+/* ------------------------------------------------------------------ */
+/* pair arithmetic                                                     */
+/* ------------------------------------------------------------------ */
+
+static float min_image(float d, float L, float h)
+{
+    if (d > h) return d - L;
+    if (d < -h) return d + L;
+    return d;
+}
+
+static float pos_d2(const float *x, const float *y, const float *z,
+                    int64_t i, int64_t j, float L, float h)
+{
+    float dx = min_image(x[i] - x[j], L, h);
+    float dy = min_image(y[i] - y[j], L, h);
+    float dz = min_image(z[i] - z[j], L, h);
+    float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    float t = sx + sy;
+    return t + sz;
+}
+
+static float vel_d2(const float *vx, const float *vy, const float *vz,
+                    int64_t i, int64_t j)
+{
+    float dx = vx[i] - vx[j], dy = vy[i] - vy[j], dz = vz[i] - vz[j];
+    float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    float t = sx + sy;
+    return t + sz;
+}
+
+typedef struct {
+    const float *x, *y, *z, *vx, *vy, *vz;
+    float L, h;
+} parts_t;
+
+static float phase_d2(const parts_t *p, int64_t i, int64_t j, float a, float c)
+{
+    float Dx = pos_d2(p->x, p->y, p->z, i, j, p->L, p->h);
+    float Dv = vel_d2(p->vx, p->vy, p->vz, i, j);
+    float u = a * Dx, w = c * Dv;
+    return u + w;
+}
+
+/* ------------------------------------------------------------------ */
+/* union-find whose root is always the smallest element                */
+/* ------------------------------------------------------------------ */
+
+static int64_t uf_find(int64_t *parent, int64_t i)
+{
+    while (parent[i] != i) {
+        parent[i] = parent[parent[i]];
+        i = parent[i];
+    }
+    return i;
+}
+
+static void uf_union(int64_t *parent, int64_t a, int64_t b)
+{
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a < b) parent[b] = a; else parent[a] = b;
+}
+
+/* ------------------------------------------------------------------ */
+/* 3D FoF                                                              */
+/* ------------------------------------------------------------------ */
+
+static int check_positions(const float *x, const float *y, const float *z,
+                           int64_t n, float L)
+{
+    for (int64_t i = 0; i < n; i++) {
+        if (!(x[i] >= 0.0f && x[i] < L)) return -2;
+        if (!(y[i] >= 0.0f && y[i] < L)) return -2;
+        if (!(z[i] >= 0.0f && z[i] < L)) return -2;
+    }
+    return 0;
+}
+
+/* All pairs.  O(n^2); reference for the grid version and for tiny boxes. */
+int oracle_fof3d_brute(const float *x, const float *y, const float *z,
+                       int64_t n, float L, float ll, int32_t *labels)
+{
+    if (n < 0 || !(L > 0.0f) || !(ll > 0.0f)) return -1;
+    if (check_positions(x, y, z, n, L)) return -2;
+    float h = 0.5f * L, ll2 = ll * ll;
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!parent) return -3;
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = i + 1; j < n; j++)
+            if (pos_d2(x, y, z, i, j, L, h) <= ll2) uf_union(parent, i, j);
+    for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
+    free(parent);
+    return 0;
+}
+
+typedef struct { int64_t key, idx; } kv_t;
+
+static int cmp_kv(const void *pa, const void *pb)
+{
+    const kv_t *a = (const kv_t *)pa, *b = (const kv_t *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return a->idx < b->idx ? -1 : (a->idx > b->idx);
+}
+
+/* first position in sorted[0..m) with key >= k */
+static int64_t lower_key(const kv_t *s, int64_t m, int64_t k)
+{
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (s[mid].key < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/*
+ * Periodic cell grid of nc^3 cells, nc chosen so that nc*ll/L < 1 - 2^-20.
+ * A pair whose computed D <= ll^2 has |xi - xj| (min image) <= ll(1 + 2^-22),
+ * so its fp64 cell coordinates differ by less than one cell along every axis
+ * and the pair sits in neighbouring cells.  Every such pair is visited.
+ */
+int oracle_fof3d(const float *x, const float *y, const float *z,
+                 int64_t n, float L, float ll, int32_t *labels)
+{
+    if (n < 0 || !(L > 0.0f) || !(ll > 0.0f)) return -1;
+    if (check_positions(x, y, z, n, L)) return -2;
+    double ratio = (double)L / (double)ll * (1.0 - ldexp(1.0, -20));
+    int64_t nc = (int64_t)ceil(ratio) - 1;
+    if (nc < 3 || nc > 2000000) return oracle_fof3d_brute(x, y, z, n, L, ll, labels);
+    float h = 0.5f * L, ll2 = ll * ll;
+    double scale = (double)nc / (double)L;
+    kv_t *s = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!s || !parent) { free(s); free(parent); return -3; }
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c[3];
+        double u[3] = { (double)x[i] * scale, (double)y[i] * scale, (double)z[i] * scale };
+        for (int a = 0; a < 3; a++) {
+            c[a] = (int64_t)floor(u[a]);
+            if (c[a] >= nc) c[a] = nc - 1;
+            if (c[a] < 0) c[a] = 0;
+        }
+        s[i].key = (c[2] * nc + c[1]) * nc + c[0];
+        s[i].idx = i;
+        parent[i] = i;
+    }
+    qsort(s, (size_t)n, sizeof(kv_t), cmp_kv);
+    int64_t start = 0;
+    while (start < n) {
+        int64_t key = s[start].key, end = start;
+        while (end < n && s[end].key == key) end++;
+        int64_t cx = key % nc, cy = (key / nc) % nc, cz = key / (nc * nc);
+        for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+            int64_t ox = (cx + dx + nc) % nc, oy = (cy + dy + nc) % nc, oz = (cz + dz + nc) % nc;
+            int64_t nk = (oz * nc + oy) * nc + ox;
+            if (nk < key) continue;          /* each cell pair once */
+            int64_t b0 = lower_key(s, n, nk);
+            for (int64_t p = start; p < end; p++)
+                for (int64_t q = b0; q < n && s[q].key == nk; q++) {
+                    if (nk == key && q <= p) continue;
+                    if (pos_d2(x, y, z, s[p].idx, s[q].idx, L, h) <= ll2)
+                        uf_union(parent, s[p].idx, s[q].idx);
+                }
+        }
+        start = end;
+    }
+    for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
+    free(s);
+    free(parent);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* exact integer moments -> dispersions and metric factors             */
+/* ------------------------------------------------------------------ */
+
+/* Correctly rounded (nearest-even) conversion; gcc's own conversion. */
+double oracle_i128_to_f64(int64_t hi, uint64_t lo)
+{
+    i128 v = ((i128)hi << 64) | (i128)lo;
+    return (double)v;
+}
+
+typedef struct {
+    float a, c;          /* 1/sigma_x^2, 1/sigma_v^2 (metric factors) */
+    float sx2, sv2;      /* sigma_x^2, sigma_v^2 */
+} norm_t;
+
+/*
+ * Positions quantised to Q = rint(x * 2^20) (fp64), taken relative to the
+ * member with the smallest index and brought to the nearest periodic image
+ * in integer arithmetic; velocities quantised to W = rint(v * 2^10).
+ * Per axis S1 = sum(delta), S2 = sum(delta^2), exact in integers;
+ * V = sum_axes (N*S2 - S1^2) = N^2 * (3D dispersion) in quantum units.
+ */
+static norm_t node_norm(const parts_t *p, const int64_t *mem, int64_t n, int64_t ref)
+{
+    const float *pc[3] = { p->x, p->y, p->z };
+    const float *vc[3] = { p->vx, p->vy, p->vz };
+    int64_t LQ = (int64_t)rint((double)p->L * 1048576.0);
+    i128 Vx = 0, Vv = 0;
+    for (int ax = 0; ax < 3; ax++) {
+        int64_t qref = (int64_t)rint((double)pc[ax][ref] * 1048576.0);
+        int64_t s1 = 0, t1 = 0;
+        i128 s2 = 0, t2 = 0;
+        for (int64_t m = 0; m < n; m++) {
+            int64_t i = mem[m];
+            int64_t d = (int64_t)rint((double)pc[ax][i] * 1048576.0) - qref;
+            if (2 * d > LQ) d -= LQ;
+            else if (2 * d <= -LQ) d += LQ;
+            s1 += d;
+            s2 += (i128)d * d;
+            int64_t w = (int64_t)rint((double)vc[ax][i] * 1024.0);
+            t1 += w;
+            t2 += (i128)w * w;
+        }
+        Vx += (i128)n * s2 - (i128)s1 * s1;
+        Vv += (i128)n * t2 - (i128)t1 * t1;
+    }
+    norm_t r;
+    double nn = (double)n * (double)n;
+    double vx = (double)Vx, vv = (double)Vv;
+    r.a = (Vx == 0) ? 1.0f : (float)((nn / vx) * 1099511627776.0);   /* 2^40 */
+    r.c = (Vv == 0) ? 1.0f : (float)((nn / vv) * 1048576.0);         /* 2^20 */
+    r.sx2 = (float)((vx / nn) * 9.094947017729282e-13);              /* 2^-40 */
+    r.sv2 = (float)((vv / nn) * 9.5367431640625e-07);                /* 2^-20 */
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* node-local position grid (fp64 unwrapped coordinates)               */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t g[3];           /* cells per axis */
+    double lo[3], cell;     /* grid origin and cell side */
+    int64_t *start;         /* [ncell + 1] */
+    int64_t *order;         /* member slots sorted by cell */
+    int64_t *cellof;        /* cell of each member slot */
+} grid_t;
+
+static void grid_free(grid_t *g)
+{
+    free(g->start); free(g->order); free(g->cellof);
+    memset(g, 0, sizeof(*g));
+}
+
+/* Returns 0, or 1 if the node spans too much of the box for a grid. */
+static int grid_build(grid_t *g, const parts_t *p, const int64_t *mem, int64_t n,
+                      int64_t ref, double *ux, double *uy, double *uz)
+{
+    const float *pc[3] = { p->x, p->y, p->z };
+    double *u[3] = { ux, uy, uz };
+    double L = p->L, ext[3], hi[3];
+    memset(g, 0, sizeof(*g));
+    for (int a = 0; a < 3; a++) {
+        g->lo[a] = 1e300; hi[a] = -1e300;
+        for (int64_t m = 0; m < n; m++) {
+            double d = (double)pc[a][mem[m]] - (double)pc[a][ref];
+            if (d >= 0.5 * L) d -= L; else if (d < -0.5 * L) d += L;
+            u[a][m] = d;
+            if (d < g->lo[a]) g->lo[a] = d;
+            if (d > hi[a]) hi[a] = d;
+        }
+        ext[a] = hi[a] - g->lo[a];
+        if (ext[a] > 0.25 * L) return 1;      /* near-percolating: brute force */
+    }
+    double emax = fmax(ext[0], fmax(ext[1], ext[2]));
+    double per = cbrt((double)n / 8.0);
+    if (per < 1.0) per = 1.0;
+    g->cell = emax / per;
+    if (!(g->cell > 0.0)) g->cell = 1.0;
+    int64_t ncell;
+    for (;;) {
+        ncell = 1;
+        for (int a = 0; a < 3; a++) {
+            g->g[a] = (int64_t)floor(ext[a] / g->cell) + 1;
+            ncell *= g->g[a];
+        }
+        if (ncell <= 4 * n + 64) break;
+        g->cell *= 1.5;
+    }
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    g->cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t m = 0; m < n; m++) {
+        int64_t c[3];
+        for (int a = 0; a < 3; a++) {
+            c[a] = (int64_t)floor((u[a][m] - g->lo[a]) / g->cell);
+            if (c[a] >= g->g[a]) c[a] = g->g[a] - 1;
+            if (c[a] < 0) c[a] = 0;
+        }
+        g->cellof[m] = (c[2] * g->g[1] + c[1]) * g->g[0] + c[0];
+        g->start[g->cellof[m] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; c++) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t m = 0; m < n; m++) g->order[fill[g->cellof[m]]++] = m;
+    free(fill);
+    return 0;
+}
+
+/*
+ * Lower bound on the computed a*Dx for any pair whose cells have at least r
+ * whole cells between them along some axis, so that the true min-image
+ * separation is >= r*cell.  1e-3 relative slack and an
+ * absolute slack of 8 fp32 ulps of L cover all rounding of positions,
+ * differences, squares and sums.
+ */
+static double ring_bound(const grid_t *g, const parts_t *p, int64_t r, double a)
+{
+    double sep = (double)r * g->cell - 8.0 * (double)p->L * ldexp(1.0, -23);
+    if (sep <= 0.0) return 0.0;
+    return a * sep * sep * (1.0 - 1e-3);
+}
+
+/* visit all member slots in the Chebyshev shell at distance r around cell c */
+typedef void (*visit_fn)(void *ctx, int64_t slot);
+
+static void visit_ring(const grid_t *g, int64_t cell, int64_t r, visit_fn fn, void *ctx)
+{
+    int64_t cx = cell % g->g[0], cy = (cell / g->g[0]) % g->g[1], cz = cell / (g->g[0] * g->g[1]);
+    for (int64_t dz = -r; dz <= r; dz++) {
+        int64_t z = cz + dz;
+        if (z < 0 || z >= g->g[2]) continue;
+        for (int64_t dy = -r; dy <= r; dy++) {
+            int64_t y = cy + dy;
+            if (y < 0 || y >= g->g[1]) continue;
+            int64_t adz = dz < 0 ? -dz : dz, ady = dy < 0 ? -dy : dy;
+            int on_face = (adz == r || ady == r);
+            for (int64_t dx = -r; dx <= r; dx++) {
+                int64_t adx = dx < 0 ? -dx : dx;
+                if (!on_face && adx != r) continue;
+                int64_t x = cx + dx;
+                if (x < 0 || x >= g->g[0]) continue;
+                int64_t c = (z * g->g[1] + y) * g->g[0] + x;
+                for (int64_t q = g->start[c]; q < g->start[c + 1]; q++) fn(ctx, g->order[q]);
+            }
+        }
+    }
+}
+
+static int64_t grid_max_ring(const grid_t *g)
+{
+    int64_t m = g->g[0];
+    if (g->g[1] > m) m = g->g[1];
+    if (g->g[2] > m) m = g->g[2];
+    return m;
+}
+
+typedef struct {
+    const parts_t *p;
+    const int64_t *mem;
+    int64_t self;
+    float a, c, best;
+} nn_ctx;
+
+static void nn_visit(void *vctx, int64_t slot)
+{
+    nn_ctx *q = (nn_ctx *)vctx;
+    if (slot == q->self) return;
+    float d = phase_d2(q->p, q->mem[q->self], q->mem[slot], q->a, q->c);
+    if (d < q->best) q->best = d;
+}
+
+typedef struct {
+    const parts_t *p;
+    const int64_t *mem;
+    int64_t self;
+    float a, c, l2;
+    int64_t *parent;
+} link_ctx;
+
+static void link_visit(void *vctx, int64_t slot)
+{
+    link_ctx *q = (link_ctx *)vctx;
+    if (slot <= q->self) return;
+    if (phase_d2(q->p, q->mem[q->self], q->mem[slot], q->a, q->c) <= q->l2)
+        uf_union(q->parent, q->self, slot);
+}
+
+static int cmp_f32(const void *pa, const void *pb)
+{
+    float a = *(const float *)pa, b = *(const float *)pb;
+    return (a > b) - (a < b);
+}
+
+/* k = ceil(f n) in exact integer arithmetic (f in parts per million), clamped. */
+int64_t oracle_select_rank(int64_t n, double f)
+{
+    int64_t ppm = llround(f * 1e6);
+    int64_t k = (n * ppm + 999999) / 1000000;
+    if (k < 1) k = 1;
+    if (k > n) k = n;
+    return k;
+}
+
+/* ------------------------------------------------------------------ */
+/* hierarchical 6D phase-space FoF                                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t *mem;        /* member indices, ascending */
+    int64_t n;
+    int32_t level;
+    int64_t parent;      /* creation index of the parent, -1 for level 0 */
+    float l2, a, c, sx2, sv2;
+} node_t;
+
+typedef struct {
+    node_t *v;
+    int64_t n, cap;
+} nodevec;
+
+static int nv_push(nodevec *nv, node_t nd)
+{
+    if (nv->n == nv->cap) {
+        int64_t nc = nv->cap ? 2 * nv->cap : 1024;
+        node_t *t = (node_t *)realloc(nv->v, sizeof(node_t) * (size_t)nc);
+        if (!t) return -3;
+        nv->v = t; nv->cap = nc;
+    }
+    nv->v[nv->n++] = nd;
+    return 0;
+}
+
+static int cmp_i64(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    return (a > b) - (a < b);
+}
+
+/*
+ * Split one node: fills its l2/a/c/sigma fields and appends its children
+ * (with member lists in ascending index order) to the node vector.
+ * brute_max: nodes with at most this many members use all-pairs loops.
+ */
+static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub,
+                      double f, int64_t brute_max)
+{
+    node_t nd = nv->v[id];
+    int64_t n = nd.n;
+    const int64_t *mem = nd.mem;
+    norm_t nm = node_norm(p, mem, n, mem[0]);       /* mem[0] is the smallest index */
+    float a = nm.a, c = nm.c;
+
+    float *d2 = (float *)malloc(sizeof(float) * (size_t)n);
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    double *ux = (double *)malloc(sizeof(double) * (size_t)n * 3);
+    if (!d2 || !parent || !ux) { free(d2); free(parent); free(ux); return -3; }
+
+    grid_t g;
+    int brute = (n <= brute_max);
+    if (!brute) brute = grid_build(&g, p, mem, n, mem[0], ux, ux + n, ux + 2 * n);
+
+    /* nearest-neighbour distance of every member */
+    if (brute) {
+        for (int64_t i = 0; i < n; i++) {
+            float best = INFINITY;
+            for (int64_t j = 0; j < n; j++) {
+                if (j == i) continue;
+                float d = phase_d2(p, mem[i], mem[j], a, c);
+                if (d < best) best = d;
+            }
+            d2[i] = best;
+        }
+    } else {
+        int64_t rmax = grid_max_ring(&g);
+        for (int64_t i = 0; i < n; i++) {
+            nn_ctx q = { p, mem, i, a, c, INFINITY };
+            for (int64_t r = 0; r <= rmax; r++) {
+                /* cells r rings away are separated by >= r-1 whole cells */
+                if (r >= 1 && ring_bound(&g, p, r - 1, (double)a) > (double)q.best) break;
+                visit_ring(&g, g.cellof[i], r, nn_visit, &q);
+            }
+            d2[i] = q.best;
+        }
+    }
+
+    /* the linking length: k-th smallest nearest-neighbour distance */
+    int64_t k = oracle_select_rank(n, f);
+    float *sorted = (float *)malloc(sizeof(float) * (size_t)n);
+    memcpy(sorted, d2, sizeof(float) * (size_t)n);
+    qsort(sorted, (size_t)n, sizeof(float), cmp_f32);
+    float l2 = sorted[k - 1];
+    free(sorted);
+
+    /* link all pairs within l2 */
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
+    if (brute) {
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = i + 1; j < n; j++)
+                if (phase_d2(p, mem[i], mem[j], a, c) <= l2) uf_union(parent, i, j);
+    } else {
+        int64_t rmax = grid_max_ring(&g);
+        for (int64_t i = 0; i < n; i++) {
+            if (!(d2[i] <= l2)) continue;            /* no neighbour within l: cannot link */
+            link_ctx q = { p, mem, i, a, c, l2, parent };
+            for (int64_t r = 0; r <= rmax; r++) {
+                if (r >= 1 && ring_bound(&g, p, r - 1, (double)a) > (double)l2) break;
+                visit_ring(&g, g.cellof[i], r, link_visit, &q);
+            }
+        }
+        grid_free(&g);
+    }
+
+    nv->v[id].l2 = l2; nv->v[id].a = a; nv->v[id].c = c;
+    nv->v[id].sx2 = nm.sx2; nv->v[id].sv2 = nm.sv2;
+
+    /* components; member slots are in ascending index order, so the root
+       (smallest slot) is also the smallest particle index */
+    int64_t *count = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) count[uf_find(parent, i)]++;
+    int rc = 0;
+    for (int64_t r = 0; r < n && rc == 0; r++) {
+        if (parent[r] != r) continue;
+        if (count[r] < min_sub || count[r] == n) continue;
+        node_t ch;
+        memset(&ch, 0, sizeof(ch));
+        ch.n = count[r];
+        ch.level = nd.level + 1;
+        ch.parent = id;
+        ch.mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)ch.n);
+        int64_t w = 0;
+        for (int64_t i = r; i < n; i++)
+            if (uf_find(parent, i) == r) ch.mem[w++] = mem[i];
+        rc = nv_push(nv, ch);
+    }
+    free(count); free(d2); free(parent); free(ux);
+    return rc;
+}
+
+typedef struct { int64_t key; int64_t id; } nkey_t;
+
+static int cmp_nkey(const void *pa, const void *pb)
+{
+    const nkey_t *a = (const nkey_t *)pa, *b = (const nkey_t *)pb;
+    return (a->key > b->key) - (a->key < b->key);
+}
+
+/*
+ * Full hierarchy.  Outputs (caller-allocated, capacity cap), canonical order
+ * sorted by (level, smallest member index):
+ *   level, min_index, parent (canonical index, -1 at level 0), size,
+ *   l2, a, c, sx2, sv2 per node; deepest[n] = canonical index of the deepest
+ *   node containing each particle, or -1.
+ * Returns 0, -1 bad argument, -2 range, -3 memory, -4 capacity (n_nodes is
+ * still written so the caller can retry).
+ */
+int oracle_phase_fof(const float *x, const float *y, const float *z,
+                     const float *vx, const float *vy, const float *vz,
+                     int64_t n, float L, const int32_t *fof_labels,
+                     int32_t min_group, int32_t min_sub, double f, int64_t brute_max,
+                     int64_t cap, int32_t *level, int32_t *min_index, int32_t *parent,
+                     int32_t *size, float *l2, float *fa, float *fc, float *sx2, float *sv2,
+                     int32_t *deepest, int64_t *n_nodes)
+{
+    if (n < 0 || !(L > 0.0f) || min_group < 2 || min_sub < 2 || !(f > 0.0 && f <= 1.0))
+        return -1;
+    if (check_positions(x, y, z, n, L)) return -2;
+    for (int64_t i = 0; i < n; i++) {
+        if (fof_labels[i] < 0 || fof_labels[i] >= n) return -1;
+        if (!(fabsf(vx[i]) < 1048576.0f && fabsf(vy[i]) < 1048576.0f && fabsf(vz[i]) < 1048576.0f))
+            return -2;
+    }
+    parts_t p = { x, y, z, vx, vy, vz, L, 0.5f * L };
+
+    /* level-0 nodes: 3D groups with at least min_group members */
+    int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) cnt[fof_labels[i]]++;
+    nodevec nv = { 0, 0, 0 };
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) slot[i] = -1;
+    int rc = 0;
+    for (int64_t r = 0; r < n && rc == 0; r++) {
+        if (cnt[r] >= min_group) {
+            node_t nd;
+            memset(&nd, 0, sizeof(nd));
+            nd.n = 0; nd.level = 0; nd.parent = -1;
+            nd.mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)cnt[r]);
+            slot[r] = nv.n;
+            rc = nv_push(&nv, nd);
+        }
+    }
+    for (int64_t i = 0; i < n && rc == 0; i++) {
+        int64_t s = slot[fof_labels[i]];
+        if (s >= 0) nv.v[s].mem[nv.v[s].n++] = i;
+    }
+    free(cnt); free(slot);
+
+    for (int64_t id = 0; id < nv.n && rc == 0; id++)
+        rc = split_node(&nv, id, &p, min_sub, f, brute_max);
+
+    *n_nodes = nv.n;
+    if (rc == 0 && nv.n > cap) rc = -4;
+    if (rc == 0) {
+        nkey_t *ord = (nkey_t *)malloc(sizeof(nkey_t) * (size_t)(nv.n > 0 ? nv.n : 1));
+        int64_t *canon = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv.n > 0 ? nv.n : 1));
+        for (int64_t i = 0; i < nv.n; i++) {
+            ord[i].key = ((int64_t)nv.v[i].level << 32) | nv.v[i].mem[0];
+            ord[i].id = i;
+        }
+        qsort(ord, (size_t)nv.n, sizeof(nkey_t), cmp_nkey);
+        for (int64_t r = 0; r < nv.n; r++) canon[ord[r].id] = r;
+        for (int64_t i = 0; i < n; i++) deepest[i] = -1;
+        for (int64_t r = 0; r < nv.n; r++) {
+            node_t *nd = &nv.v[ord[r].id];
+            level[r] = nd->level;
+            min_index[r] = (int32_t)nd->mem[0];
+            parent[r] = nd->parent < 0 ? -1 : (int32_t)canon[nd->parent];
+            size[r] = (int32_t)nd->n;
+            l2[r] = nd->l2; fa[r] = nd->a; fc[r] = nd->c;
+            sx2[r] = nd->sx2; sv2[r] = nd->sv2;
+            for (int64_t m = 0; m < nd->n; m++) deepest[nd->mem[m]] = (int32_t)r;
+        }
+        free(ord); free(canon);
+    }
+    for (int64_t i = 0; i < nv.n; i++) free(nv.v[i].mem);
+    free(nv.v);
+    return rc;
+}
+
+/* Nearest-neighbour distances of one explicit member set (for pins). */
+int oracle_node_nn(const float *x, const float *y, const float *z,
+                   const float *vx, const float *vy, const float *vz, float L,
+                   const int64_t *mem, int64_t n, float a, float c, float *d2)
+{
+    parts_t p = { x, y, z, vx, vy, vz, L, 0.5f * L };
+    for (int64_t i = 0; i < n; i++) {
+        float best = INFINITY;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            float d = phase_d2(&p, mem[i], mem[j], a, c);
+            if (d < best) best = d;
+        }
+        d2[i] = best;
+    }
+    return 0;
+}
+
+/* Metric factors of one explicit member set (mem ascending). */
+int oracle_node_norm(const float *x, const float *y, const float *z,
+                     const float *vx, const float *vy, const float *vz, float L,
+                     const int64_t *mem, int64_t n, float *out4)
+{
+    parts_t p = { x, y, z, vx, vy, vz, L, 0.5f * L };
+    norm_t r = node_norm(&p, mem, n, mem[0]);
+    out4[0] = r.a; out4[1] = r.c; out4[2] = r.sx2; out4[3] = r.sv2;
+    return 0;
+}
