@@ -157,18 +157,20 @@ static int64_t lower_key(const kv_t *s, int64_t m, int64_t k)
 }
 
 /*
- * Periodic cell grid of nc^3 cells, nc chosen so that nc*ll/L < 1 - 2^-20.
- * A pair whose computed D <= ll^2 has |xi - xj| (min image) <= ll(1 + 2^-22),
- * so its fp64 cell coordinates differ by less than one cell along every axis
- * and the pair sits in neighbouring cells.  Every such pair is visited.
+ * Periodic cell grid of nc^3 cells whose side L/nc is at least
+ * ll (1 + 2^-20) + L 2^-22.  A pair whose computed D <= ll^2 has a computed
+ * per-axis |dx| <= ll (1 + 2^-23); the computed difference is within half an
+ * ulp of L of the true min-image separation (the image shift itself is exact),
+ * so the true separation is below one cell side along every axis and the
+ * pair sits in neighbouring cells.  Every such pair is visited.
  */
 int oracle_fof3d(const float *x, const float *y, const float *z,
                  int64_t n, float L, float ll, int32_t *labels)
 {
     if (n < 0 || !(L > 0.0f) || !(ll > 0.0f)) return -1;
     if (check_positions(x, y, z, n, L)) return -2;
-    double ratio = (double)L / (double)ll * (1.0 - ldexp(1.0, -20));
-    int64_t nc = (int64_t)ceil(ratio) - 1;
+    double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + (double)L * ldexp(1.0, -22);
+    int64_t nc = (int64_t)floor((double)L / side_min);
     if (nc < 3 || nc > 2000000) return oracle_fof3d_brute(x, y, z, n, L, ll, labels);
     float h = 0.5f * L, ll2 = ll * ll;
     double scale = (double)nc / (double)L;
