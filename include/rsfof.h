@@ -1,0 +1,146 @@
+/*
+ * rsfof.h -- C ABI of the MI355X friends-of-friends halo-finding core.
+ *
+ * The library implements the two data-parallel steps that the MPI-Rockstar
+ * paper (arXiv:2412.18629, Parallelization section) describes for each
+ * process's sub-box: a 3D friends-of-friends pass that finds overdense
+ * regions, then subhalo finding inside every FoF halo using 6D phase-space
+ * information (Rockstar's hierarchical phase-space FoF, the method the paper
+ * cites in its Summary).  All compute runs in HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers are DEVICE pointers unless marked (host).
+ *   - Inputs are caller-owned and only read.  Positions are fp32 SoA arrays
+ *     x[n], y[n], z[n] in [0, box); velocities are fp32 SoA vx[n], vy[n],
+ *     vz[n] in km/s with |v| < 2^20.
+ *   - Argument errors are reported before any device work.  On any error
+ *     the return value is negative, outputs are left untouched, and nothing
+ *     leaks.  Out-of-range or non-finite coordinates are detected on the
+ *     device before any output is written and reported as RS_ERANGE.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  The library
+ *     keeps one grow-only workspace per device; calls that overlap on one
+ *     device from several host threads are not supported.
+ *
+ * Pair arithmetic (fixed, identical in every kernel):
+ *   dx = fl(xi - xj) followed by one periodic shift (dx > box/2: dx - box;
+ *   dx < -box/2: dx + box); D = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)),
+ *   no fused multiply-add, round to nearest even, denormals kept.
+ */
+#ifndef RSFOF_H
+#define RSFOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RS_OK = 0,
+    RS_EINVAL = -1,     /* bad argument (NULL pointer, size, parameter range) */
+    RS_ERANGE = -2,     /* a coordinate outside [0, box), non-finite, or |v| >= 2^20 */
+    RS_ENOMEM = -3,     /* device allocation failed */
+    RS_EDEVICE = -4,    /* no usable HIP device, or a HIP runtime error */
+    RS_EINTERNAL = -5,  /* internal capacity or consistency failure */
+    RS_ENOTIMPL = -6    /* requested mode not available */
+} rs_status;
+
+/* Execution forms of rs_phase_fof_batch.  All forms return identical results. */
+enum {
+    RS_PLAIN = 0,    /* one level-0 group per launch sequence, host-driven */
+    RS_BATCHED = 1,  /* all groups and levels through size-bucketed kernels */
+    RS_LEARNED = 2   /* batched, linking length proposed by the MLP and verified
+                        by exact counting in a bracket (implies RS_BATCHED) */
+};
+
+/*
+ * rs_fof3d -- 3D friends-of-friends over one periodic box (paper,
+ * Parallelization section: "each process performs 3D FoF").
+ *
+ * Groups are the connected components of the pair relation D(i,j) <= ll^2
+ * with ll = link_len (an absolute length; a caller following the paper's
+ * convention passes b times the mean interparticle spacing).
+ *   x, y, z    [n] fp32 positions, 0 <= x < box.
+ *   n          0 <= n < 2^31.
+ *   box        periodic box side, > 0.
+ *   link_len   0 < link_len < box / 2.
+ *   labels     [n] int32 output, caller-allocated: the smallest particle
+ *              index of each particle's group.
+ *   n_groups   (host, optional) number of groups, including singletons.
+ * Synchronous with respect to `stream` on return.
+ */
+int rs_fof3d(const float* x, const float* y, const float* z, int64_t n,
+             float box, float link_len, int32_t* labels, int64_t* n_groups,
+             void* stream);
+
+/*
+ * Node hierarchy returned by rs_phase_fof_batch.  The struct lives in host
+ * memory; every array lives in ONE library-owned device allocation, released
+ * only by rs_free.
+ *
+ * Nodes are in canonical order, sorted by (level, min_index).  A level-0
+ * node is a 3D group with at least min_group members; a node's children are
+ * the components (>= min_sub members, not the whole node) of its 6D split.
+ */
+typedef struct rs_tree {
+    int64_t n_nodes;
+    int64_t n_particles;
+    int32_t* level;      /* [n_nodes] recursion depth, 0 for a 3D group */
+    int32_t* min_index;  /* [n_nodes] smallest member particle index */
+    int32_t* parent;     /* [n_nodes] index of the parent node, -1 at level 0 */
+    int32_t* size;       /* [n_nodes] member count */
+    float* l2;           /* [n_nodes] squared 6D linking length that split the node */
+    float* a;            /* [n_nodes] position metric factor 1/sigma_x^2 */
+    float* c;            /* [n_nodes] velocity metric factor 1/sigma_v^2 */
+    float* sx2;          /* [n_nodes] position dispersion sigma_x^2, (Mpc/h)^2 */
+    float* sv2;          /* [n_nodes] velocity dispersion sigma_v^2, (km/s)^2 */
+    int32_t* deepest;    /* [n_particles] deepest node containing the particle, or -1 */
+    int64_t n_accepted;  /* RS_LEARNED: nodes whose proposed bracket held */
+    int64_t n_fallback;  /* RS_LEARNED: nodes that fell back to the full search */
+    int64_t n_levels;    /* number of levels (max level + 1), 0 if no nodes */
+} rs_tree;
+
+/*
+ * rs_phase_fof_batch -- hierarchical 6D phase-space FoF inside every 3D group
+ * (paper, Parallelization section: subhalo finding for each FoF halo using
+ * 6D phase-space information; method of the cited Rockstar paper).
+ *
+ * For each node: dispersions sigma_x^2, sigma_v^2 from exact integer moments
+ * (positions quantised to 2^-20 relative to the node's smallest-index member
+ * in the nearest periodic image, velocities to 2^-10); metric
+ * d^2 = fl(fl(a*Dx) + fl(c*Dv)), a = 1/sigma_x^2, c = 1/sigma_v^2 (fp32);
+ * l^2 = the k-th smallest nearest-neighbour d^2 of the members, k = ceil(f n);
+ * members are linked when d^2 <= l^2; components of >= min_sub members other
+ * than the whole node become children and are split in turn.
+ *
+ *   x..vz       [n] fp32 positions and velocities.
+ *   fof_labels  [n] int32 group ids in [0, n) (rs_fof3d labels).
+ *   min_group   >= 2, smallest 3D group that is split (paper configs: 10).
+ *   min_sub     >= 2, smallest child kept (10).
+ *   f           0 < f <= 1, linked fraction (0.7).
+ *   flags       RS_PLAIN, RS_BATCHED or RS_LEARNED.
+ *   model       (host) weights blob from rs_model_pack for RS_LEARNED, else NULL.
+ *   out         (host) receives a new rs_tree* (release with rs_free).
+ * Returns after synchronising `stream`.
+ */
+int rs_phase_fof_batch(const float* x, const float* y, const float* z,
+                       const float* vx, const float* vy, const float* vz,
+                       int64_t n, float box, const int32_t* fof_labels,
+                       int32_t min_group, int32_t min_sub, double f,
+                       uint32_t flags, const void* model, rs_tree** out,
+                       void* stream);
+
+/* Releases an rs_tree* (struct and device arrays).  NULL is a no-op. */
+void rs_free(void* p);
+
+/* Static description of a status code. */
+const char* rs_strerror(int status);
+
+/* Library version string (static). */
+const char* rs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSFOF_H */

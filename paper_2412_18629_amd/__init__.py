@@ -1,0 +1,167 @@
+"""MI355X friends-of-friends halo-finding core: Python binding of librsfof.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+kernels of ``librsfof.so``; PyTorch supplies device memory and streams.  If
+the library has not been built, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsfof.so")
+
+RS_OK, RS_EINVAL, RS_ERANGE, RS_ENOMEM, RS_EDEVICE, RS_EINTERNAL, RS_ENOTIMPL = (
+    0, -1, -2, -3, -4, -5, -6)
+RS_PLAIN, RS_BATCHED, RS_LEARNED = 0, 1, 2
+
+EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version")
+
+
+class RsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+class _Tree(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_particles", ctypes.c_int64),
+                ("level", ctypes.c_void_p), ("min_index", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p), ("size", ctypes.c_void_p),
+                ("l2", ctypes.c_void_p), ("a", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("sx2", ctypes.c_void_p), ("sv2", ctypes.c_void_p),
+                ("deepest", ctypes.c_void_p), ("n_accepted", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int64), ("n_levels", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load librsfof.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2412_18629_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, f32, f64, u32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_float, ctypes.c_double, ctypes.c_uint32)
+    lib.rs_fof3d.argtypes = [P, P, P, i64, f32, f32, P, ctypes.POINTER(i64), P]
+    lib.rs_fof3d.restype = ctypes.c_int
+    lib.rs_phase_fof_batch.argtypes = [P, P, P, P, P, P, i64, f32, P, i32, i32, f64, u32, P,
+                                       ctypes.POINTER(ctypes.POINTER(_Tree)), P]
+    lib.rs_phase_fof_batch.restype = ctypes.c_int
+    lib.rs_free.argtypes = [P]
+    lib.rs_free.restype = None
+    lib.rs_strerror.argtypes = [ctypes.c_int]
+    lib.rs_strerror.restype = ctypes.c_char_p
+    lib.rs_version.argtypes = []
+    lib.rs_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().rs_strerror(int(status)).decode()
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rs_fof3d(x, y, z, box, link_len, labels=None, stream=None):
+    """3D FoF labels (int32 device tensor, smallest member index per group)
+    and the number of groups."""
+    lib = load()
+    n = x.numel()
+    for t, nm in ((y, "y"), (z, "z")):
+        if t.numel() != n:
+            raise ValueError(f"{nm} size differs from x")
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=x.device)
+    ptrs = [_dev(t, torch.float32, nm) for t, nm in ((x, "x"), (y, "y"), (z, "z"))]
+    ng = ctypes.c_int64(-1)
+    rc = lib.rs_fof3d(*ptrs, n, float(box), float(link_len), _dev(labels, torch.int32, "labels"),
+                      ctypes.byref(ng), _stream(stream))
+    if rc != RS_OK:
+        raise RsError(rc, "rs_fof3d")
+    return labels, int(ng.value)
+
+
+class _DevArray:
+    """Zero-copy view descriptor of a device array owned by the library."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr,
+                                         "data": (int(ptr or 0), False), "version": 3,
+                                         "strides": None}
+
+
+def _copy_out(ptr, n, dtype, device):
+    if n == 0:
+        return torch.empty(0, dtype=dtype, device=device)
+    typestr = {torch.int32: "<i4", torch.float32: "<f4"}[dtype]
+    view = torch.as_tensor(_DevArray(ptr, n, typestr), device=device)
+    return view.clone()
+
+
+TREE_FIELDS = (("level", torch.int32), ("min_index", torch.int32), ("parent", torch.int32),
+               ("size", torch.int32), ("l2", torch.float32), ("a", torch.float32),
+               ("c", torch.float32), ("sx2", torch.float32), ("sv2", torch.float32))
+
+
+def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=0.7,
+                       flags=RS_BATCHED, model=None, stream=None):
+    """Hierarchical 6D FoF.  Returns a dict of device tensors: the node fields
+    in canonical (level, min_index) order, ``deepest`` per particle, and the
+    statistics n_accepted, n_fallback, n_levels."""
+    lib = load()
+    n = x.numel()
+    arrs = (x, y, z, vx, vy, vz)
+    names = ("x", "y", "z", "vx", "vy", "vz")
+    for t, nm in zip(arrs, names):
+        if t.numel() != n:
+            raise ValueError(f"{nm} size differs from x")
+    ptrs = [_dev(t, torch.float32, nm) for t, nm in zip(arrs, names)]
+    lab = _dev(fof_labels, torch.int32, "fof_labels")
+    if model is not None and not isinstance(model, (bytes, bytearray)):
+        raise TypeError("model must be a bytes blob")
+    mbuf = ctypes.create_string_buffer(bytes(model), len(model)) if model is not None else None
+    out = ctypes.POINTER(_Tree)()
+    st = _stream(stream)
+    rc = lib.rs_phase_fof_batch(*ptrs, n, float(box), lab, int(min_group), int(min_sub),
+                                float(f), int(flags),
+                                ctypes.cast(mbuf, ctypes.c_void_p) if mbuf is not None else None,
+                                ctypes.byref(out), st)
+    if rc != RS_OK:
+        raise RsError(rc, "rs_phase_fof_batch")
+    try:
+        t = out.contents
+        m = int(t.n_nodes)
+        res = {k: _copy_out(getattr(t, k), m, dt, x.device) for k, dt in TREE_FIELDS}
+        res["deepest"] = _copy_out(t.deepest, n, torch.int32, x.device)
+        res["n_accepted"] = int(t.n_accepted)
+        res["n_fallback"] = int(t.n_fallback)
+        res["n_levels"] = int(t.n_levels)
+        torch.cuda.current_stream().synchronize()
+    finally:
+        lib.rs_free(out)
+    return res

@@ -1,0 +1,82 @@
+// api.hip -- the extern "C" entry points: argument checks, then dispatch to
+// the device pipelines.  No device work happens before the checks pass.
+#include <math.h>
+#include <stdlib.h>
+
+#include "common.h"
+
+namespace rs {
+int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
+              int32_t* labels, int64_t* n_groups, hipStream_t st);
+int phase_run(const float* x, const float* y, const float* z, const float* vx,
+              const float* vy, const float* vz, int64_t n, float L, const int32_t* labels,
+              int32_t min_group, int32_t min_sub, double f, uint32_t flags, const void* model,
+              rs_tree** out, hipStream_t st);
+void tree_release(rs_tree* t);
+
+static int device_ready() {
+    int cnt = 0;
+    hipError_t e = hipGetDeviceCount(&cnt);
+    if (e != hipSuccess || cnt < 1) {
+        (void)hipGetLastError();
+        return RS_EDEVICE;
+    }
+    return RS_OK;
+}
+}  // namespace rs
+
+extern "C" {
+
+int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float box,
+             float link_len, int32_t* labels, int64_t* n_groups, void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31) return RS_EINVAL;
+    if (!(box > 0.0f) || !isfinite(box)) return RS_EINVAL;
+    if (!(link_len > 0.0f) || !(link_len < 0.5f * box)) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !labels)) return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    if (n == 0) {
+        if (n_groups) *n_groups = 0;
+        return RS_OK;
+    }
+    return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
+                         static_cast<hipStream_t>(stream));
+}
+
+int rs_phase_fof_batch(const float* x, const float* y, const float* z, const float* vx,
+                       const float* vy, const float* vz, int64_t n, float box,
+                       const int32_t* fof_labels, int32_t min_group, int32_t min_sub, double f,
+                       uint32_t flags, const void* model, rs_tree** out, void* stream) {
+    if (!out) return RS_EINVAL;
+    if (n < 0 || n >= (int64_t)1 << 31) return RS_EINVAL;
+    if (!(box > 0.0f) || !isfinite(box)) return RS_EINVAL;
+    if (min_group < 2 || min_sub < 2) return RS_EINVAL;
+    if (!(f > 0.0 && f <= 1.0)) return RS_EINVAL;
+    if (flags > RS_LEARNED) return RS_EINVAL;
+    if (flags == RS_LEARNED && !model) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !fof_labels)) return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,
+                         model, out, static_cast<hipStream_t>(stream));
+}
+
+void rs_free(void* p) {
+    if (!p) return;
+    rs::tree_release(static_cast<rs_tree*>(p));
+}
+
+const char* rs_strerror(int status) {
+    switch (status) {
+        case RS_OK: return "success";
+        case RS_EINVAL: return "invalid argument";
+        case RS_ERANGE: return "coordinate out of range or not finite";
+        case RS_ENOMEM: return "device memory allocation failed";
+        case RS_EDEVICE: return "no usable HIP device or HIP runtime error";
+        case RS_EINTERNAL: return "internal capacity or consistency failure";
+        case RS_ENOTIMPL: return "mode not implemented";
+        default: return "unknown status";
+    }
+}
+
+const char* rs_version(void) { return "rsfof 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// common.h -- shared device helpers and host plumbing of librsfof.
+//
+// Pair arithmetic follows the fixed fp32 recipe of rsfof.h: one periodic
+// shift per axis, squares summed as ((x^2 + y^2) + z^2), no contraction.
+// The library is compiled with -ffp-contract=off; the helpers below keep
+// every rounding step as a separate statement so no fusion can occur.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rsfof.h"
+
+#define RS_DEV __device__ __forceinline__
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// fp32 pair arithmetic
+// ---------------------------------------------------------------------------
+
+RS_DEV float min_image(float d, float L, float h) {
+    // one periodic image shift; identical for (i,j) and (j,i) up to sign
+    return d > h ? d - L : (d < -h ? d + L : d);
+}
+
+RS_DEV float sum_sq3(float dx, float dy, float dz) {
+    float sx = dx * dx;
+    float sy = dy * dy;
+    float sz = dz * dz;
+    float t = sx + sy;
+    return t + sz;
+}
+
+RS_DEV float pos_d2_wrap(float xi, float yi, float zi, float xj, float yj, float zj,
+                         float L, float h) {
+    return sum_sq3(min_image(xi - xj, L, h), min_image(yi - yj, L, h),
+                   min_image(zi - zj, L, h));
+}
+
+RS_DEV float pos_d2_nowrap(float xi, float yi, float zi, float xj, float yj, float zj) {
+    return sum_sq3(xi - xj, yi - yj, zi - zj);
+}
+
+RS_DEV float metric(float a, float Dx, float c, float Dv) {
+    float u = a * Dx;
+    float w = c * Dv;
+    return u + w;
+}
+
+// ---------------------------------------------------------------------------
+// lock-free union-find over an int32 parent array.
+// Invariant: parent[v] <= v, roots satisfy parent[r] == r.  Hooks always put
+// the larger root under the smaller one (CAS on the root), so no cycle can
+// form; path halving stores only ancestors, which is benign under races.
+// ---------------------------------------------------------------------------
+
+RS_DEV int uf_load(const int* p, int v) {
+    return __hip_atomic_load(p + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+RS_DEV int uf_find(int* par, int v) {
+    int cur = uf_load(par, v);
+    if (cur == v) return v;
+    int prev = v, next;
+    while (cur > (next = uf_load(par, cur))) {
+        __hip_atomic_store(par + prev, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = cur;
+        cur = next;
+    }
+    return cur;
+}
+
+RS_DEV void uf_unite(int* par, int a, int b) {
+    int ra = uf_find(par, a), rb = uf_find(par, b);
+    while (ra != rb) {
+        if (ra > rb) { int t = ra; ra = rb; rb = t; }
+        int old = atomicCAS(par + rb, rb, ra);
+        if (old == rb) return;
+        rb = uf_find(par, old);
+        ra = uf_find(par, ra);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exact 128-bit helpers
+// ---------------------------------------------------------------------------
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+// Round-to-nearest-even conversion of a signed 128-bit integer to fp64.
+RS_DEV double i128_to_f64(i128 v) {
+    bool neg = v < 0;
+    u128 u = neg ? (u128)0 - (u128)v : (u128)v;
+    if (u == 0) return 0.0;
+    uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
+    int nbits = hi ? 128 - __builtin_clzll(hi) : 64 - __builtin_clzll(lo);
+    double r;
+    if (nbits <= 53) {
+        r = (double)lo;                       // exact
+    } else {
+        int shift = nbits - 53;
+        u128 m = u >> shift;
+        u128 rem = u & (((u128)1 << shift) - 1);
+        u128 half = (u128)1 << (shift - 1);
+        if (rem > half || (rem == half && (m & 1))) m += 1;
+        if (m == ((u128)1 << 53)) { m >>= 1; shift += 1; }
+        r = __builtin_ldexp((double)(uint64_t)m, shift);
+    }
+    return neg ? -r : r;
+}
+
+}  // namespace rs
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+#define RS_HIP(expr)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) return rs::hip_status(e_);                    \
+    } while (0)
+
+#define RS_TRY(expr)                                                        \
+    do {                                                                    \
+        int s_ = (expr);                                                    \
+        if (s_ != RS_OK) return s_;                                         \
+    } while (0)
+
+namespace rs {
+
+inline int hip_status(hipError_t e) {
+    return e == hipErrorOutOfMemory ? RS_ENOMEM : RS_EDEVICE;
+}
+
+// Grow-only per-device workspace with a bump allocator.  A call reserves
+// its whole footprint once, then carves sub-buffers (256-byte aligned).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+};
+
+int arena_reserve(size_t bytes, Arena** out);   // resets the bump pointer
+void* arena_take(Arena* a, size_t bytes);       // NULL if the reservation is exceeded
+size_t arena_round(size_t bytes);
+
+template <class T>
+inline T* take(Arena* a, size_t count) {
+    return static_cast<T*>(arena_take(a, count * sizeof(T)));
+}
+
+// small pinned host scratch for reading back counters
+int host_scratch(void** out, size_t bytes);
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// device-wide primitives (prims.hip)
+size_t scan_temp_bytes(int64_t n);
+int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* temp,
+                       int32_t* total_dev, hipStream_t st);
+size_t sort_temp_bytes(int64_t n);
+int sort_pairs_u64_i32(const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                       int32_t* vout, int64_t n, int bits, void* temp, size_t temp_bytes,
+                       hipStream_t st);
+int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+
+}  // namespace rs

@@ -1,0 +1,410 @@
+// fof3d.hip -- 3D friends-of-friends over one periodic box (the per-process
+// FoF pass of the paper's Parallelization section).
+//
+// Layout and flow (all device-resident, one stream):
+//   1. keys:   each particle gets a 64-bit key (coarse cell << 3 | octant).
+//              Coarse cells have side >= ll (plus rounding slack), so every
+//              linked pair sits in neighbouring cells; octants (half-side
+//              sub-cells) have a diagonal below ll, so all particles of one
+//              octant are linked without a test (auto-link).
+//   2. sort:   key/index radix sort -> cell-sorted order; positions are
+//              gathered into sorted SoA arrays (coalesced reads later).
+//   3. tables: occupied octants and cells are enumerated by scans; an
+//              open-addressing hash maps a cell key to its octant range.
+//   4. link:   union-find over sorted slots.  An octant is one element
+//              (its first slot); octant pairs in the 27-cell neighbourhood
+//              are tested with early exit on the first linked pair, and
+//              skipped when already in one component.
+//   5. labels: flatten, smallest original index per root, scatter to the
+//              caller's label array.
+#include "common.h"
+
+namespace rs {
+
+static constexpr uint64_t HASH_EMPTY = ~0ull;
+
+RS_DEV uint64_t mix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+struct Grid3 {
+    int64_t nc;        // cells per axis
+    double scale;      // nc / L (fp64)
+    float L, h, ll2;
+    int key_bits;
+    bool autolink;     // every octant pair closer than ll
+    bool octfilter;    // octant offsets of 3 half-cells cannot link (nc >= 3)
+};
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_keys(const float* __restrict__ x, const float* __restrict__ y,
+                       const float* __restrict__ z, int64_t n, Grid3 g,
+                       uint64_t* __restrict__ keys, int32_t* __restrict__ idx,
+                       int32_t* __restrict__ err) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float p[3] = {x[i], y[i], z[i]};
+    int64_t c[3];
+    int o[3];
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        bad |= !(p[a] >= 0.0f && p[a] < g.L);
+        double u = (double)p[a] * g.scale;
+        int64_t ci = (int64_t)floor(u);
+        int64_t oi = (int64_t)floor(2.0 * u) - 2 * ci;
+        if (ci >= g.nc) { ci = g.nc - 1; oi = 1; }
+        if (ci < 0) { ci = 0; oi = 0; }
+        c[a] = ci;
+        o[a] = oi < 0 ? 0 : (oi > 1 ? 1 : (int)oi);
+    }
+    if (bad) {
+        atomicOr(err, 1);
+        c[0] = c[1] = c[2] = 0;
+    }
+    uint64_t cell = (uint64_t)((c[2] * g.nc + c[1]) * g.nc + c[0]);
+    keys[i] = (cell << 3) | (uint64_t)(o[2] << 2 | o[1] << 1 | o[0]);
+    idx[i] = (int32_t)i;
+}
+
+__global__ void k_gather3(const int32_t* __restrict__ perm, const float* __restrict__ x,
+                          const float* __restrict__ y, const float* __restrict__ z,
+                          int64_t n, float* __restrict__ sx, float* __restrict__ sy,
+                          float* __restrict__ sz) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t i = perm[s];
+    sx[s] = x[i];
+    sy[s] = y[i];
+    sz[s] = z[i];
+}
+
+// run-start flags of octants and of cells in the sorted key order
+__global__ void k_run_flags(const uint64_t* __restrict__ keys, int64_t n,
+                            int32_t* __restrict__ oflag, int32_t* __restrict__ cflag) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint64_t k = keys[s];
+    uint64_t p = s ? keys[s - 1] : ~0ull;
+    oflag[s] = (s == 0 || k != p) ? 1 : 0;
+    cflag[s] = (s == 0 || (k >> 3) != (p >> 3)) ? 1 : 0;
+}
+
+__global__ void k_tables(const uint64_t* __restrict__ keys, int64_t n,
+                         const int32_t* __restrict__ oflag, const int32_t* __restrict__ oex,
+                         const int32_t* __restrict__ cflag, const int32_t* __restrict__ cex,
+                         int32_t* __restrict__ oct_start, uint8_t* __restrict__ oct_bits,
+                         int32_t* __restrict__ cell_oct, uint64_t* __restrict__ cell_key,
+                         int32_t* __restrict__ parent, bool autolink) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (oflag[s]) {
+        int32_t o = oex[s];
+        oct_start[o] = (int32_t)s;
+        oct_bits[o] = (uint8_t)(keys[s] & 7);
+        if (cflag[s]) {
+            int32_t c = cex[s];
+            cell_oct[c] = o;
+            cell_key[c] = keys[s] >> 3;
+        }
+    }
+}
+
+// parent[s] = first slot of s's octant (auto-link) or s
+__global__ void k_parent_init(int64_t n, const int32_t* __restrict__ oflag,
+                              const int32_t* __restrict__ oex,
+                              const int32_t* __restrict__ oct_start,
+                              int32_t* __restrict__ parent, bool autolink) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (!autolink) {
+        parent[s] = (int32_t)s;
+        return;
+    }
+    int32_t o = oex[s] + oflag[s] - 1;   // octant index of slot s
+    parent[s] = oct_start[o];
+}
+
+__global__ void k_hash_insert(const uint64_t* __restrict__ cell_key, int32_t n_cell,
+                              uint64_t* __restrict__ hk, int32_t* __restrict__ hv,
+                              uint64_t mask) {
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cell) return;
+    uint64_t k = cell_key[c];
+    uint64_t slot = mix64(k) & mask;
+    for (;;) {
+        unsigned long long prev = atomicCAS((unsigned long long*)(hk + slot),
+                                            (unsigned long long)HASH_EMPTY,
+                                            (unsigned long long)k);
+        if (prev == HASH_EMPTY || prev == k) {
+            hv[slot] = c;
+            return;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
+RS_DEV int32_t hash_find(const uint64_t* __restrict__ hk, const int32_t* __restrict__ hv,
+                         uint64_t mask, uint64_t k) {
+    uint64_t slot = mix64(k) & mask;
+    for (;;) {
+        uint64_t q = hk[slot];
+        if (q == k) return hv[slot];
+        if (q == HASH_EMPTY) return -1;
+        slot = (slot + 1) & mask;
+    }
+}
+
+struct LinkArgs {
+    const int32_t* oct_start;   // [n_oct + 1]
+    const uint8_t* oct_bits;    // [n_oct]
+    const int32_t* cell_oct;    // [n_cell + 1]
+    const uint64_t* hk;
+    const int32_t* hv;
+    uint64_t mask;
+    const uint64_t* keys;       // sorted keys
+    const float *sx, *sy, *sz;  // sorted positions
+    int32_t* parent;
+    int32_t n_oct;
+    Grid3 g;
+};
+
+// one thread per octant: test it against every later octant in the
+// 27-cell neighbourhood
+template <bool AUTOLINK>
+__global__ void __launch_bounds__(256) k_link(LinkArgs A) {
+    int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= A.n_oct) return;
+    const Grid3 g = A.g;
+    int32_t s0 = A.oct_start[a], s1 = A.oct_start[a + 1];
+    uint64_t cell = A.keys[s0] >> 3;
+    int oa = A.oct_bits[a];
+    int64_t nc = g.nc;
+    int64_t cx = (int64_t)(cell % (uint64_t)nc);
+    int64_t cy = (int64_t)((cell / (uint64_t)nc) % (uint64_t)nc);
+    int64_t cz = (int64_t)(cell / ((uint64_t)nc * (uint64_t)nc));
+
+    if (!AUTOLINK) {
+        for (int32_t i = s0; i < s1; i++) {
+            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+            for (int32_t j = i + 1; j < s1; j++)
+                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2)
+                    uf_unite(A.parent, i, j);
+        }
+    }
+    for (int dz = -1; dz <= 1; dz++) {
+        int64_t nz = cz + dz;
+        nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
+        for (int dy = -1; dy <= 1; dy++) {
+            int64_t ny = cy + dy;
+            ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
+            for (int dx = -1; dx <= 1; dx++) {
+                int64_t nx = cx + dx;
+                nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
+                uint64_t nkey = (uint64_t)((nz * nc + ny) * nc + nx);
+                int32_t cid = hash_find(A.hk, A.hv, A.mask, nkey);
+                if (cid < 0) continue;
+                int32_t b0 = A.cell_oct[cid], b1 = A.cell_oct[cid + 1];
+                for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
+                    if (g.octfilter) {
+                        int ob = A.oct_bits[b];
+                        int ddx = 2 * dx + (ob & 1) - (oa & 1);
+                        int ddy = 2 * dy + ((ob >> 1) & 1) - ((oa >> 1) & 1);
+                        int ddz = 2 * dz + (ob >> 2) - (oa >> 2);
+                        if (ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 ||
+                            ddz == -3)
+                            continue;
+                    }
+                    int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
+                    if (AUTOLINK) {
+                        if (uf_find(A.parent, s0) == uf_find(A.parent, t0)) continue;
+                        bool hit = false;
+                        for (int32_t i = s0; i < s1 && !hit; i++) {
+                            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+                            for (int32_t j = t0; j < t1; j++) {
+                                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L,
+                                                g.h) <= g.ll2) {
+                                    hit = true;
+                                    break;
+                                }
+                            }
+                        }
+                        if (hit) uf_unite(A.parent, s0, t0);
+                    } else {
+                        for (int32_t i = s0; i < s1; i++) {
+                            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+                            for (int32_t j = t0; j < t1; j++)
+                                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L,
+                                                g.h) <= g.ll2)
+                                    uf_unite(A.parent, i, j);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_flatten(int64_t n, int32_t* __restrict__ parent) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    parent[s] = uf_find(parent, (int)s);
+}
+
+__global__ void k_min_index(int64_t n, const int32_t* __restrict__ parent,
+                            const int32_t* __restrict__ perm, int32_t* __restrict__ minidx) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    atomicMin(minidx + parent[s], perm[s]);
+}
+
+__global__ void k_write_labels(int64_t n, const int32_t* __restrict__ parent,
+                               const int32_t* __restrict__ perm,
+                               const int32_t* __restrict__ minidx, int32_t* __restrict__ labels,
+                               unsigned long long* __restrict__ nroots) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool root = false;
+    if (s < n) {
+        int32_t r = parent[s];
+        labels[perm[s]] = minidx[r];
+        root = (r == (int32_t)s);
+    }
+    unsigned long long b = __ballot(root);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nroots, (unsigned long long)__popcll(b));
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+static int plan_grid(float L, float ll, Grid3* g) {
+    double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + (double)L * ldexp(1.0, -22);
+    int64_t nc = (int64_t)floor((double)L / side_min);
+    if (nc < 1) nc = 1;
+    if (nc > (1 << 20)) return RS_EINVAL;
+    g->nc = nc;
+    g->scale = (double)nc / (double)L;
+    g->L = L;
+    g->h = 0.5f * L;
+    g->ll2 = ll * ll;
+    double cells = (double)nc * (double)nc * (double)nc;
+    int bits = 1;
+    while (bits < 61 && ldexp(1.0, bits) < cells) bits++;
+    g->key_bits = bits + 3;
+    double side = (double)L / (2.0 * (double)nc);
+    g->autolink = 3.0 * side * side * (1.0 + 1e-5) <= (double)ll * (double)ll * (1.0 - 1e-5);
+    g->octfilter = nc >= 3;
+    return RS_OK;
+}
+
+static uint64_t pow2_at_least(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
+              int32_t* labels, int64_t* n_groups, hipStream_t st) {
+    Grid3 g;
+    RS_TRY(plan_grid(L, ll, &g));
+    const int BT = 256;
+    // footprint (upper bounds: octants and cells <= n)
+    uint64_t hcap = pow2_at_least((uint64_t)2 * (uint64_t)n + 64);
+    size_t bytes = 0;
+    auto add = [&](size_t b) { bytes += arena_round(b); };
+    add(8 * n); add(8 * n);                 // keys in / out
+    add(4 * n); add(4 * n);                 // index in / perm
+    add(12 * n);                            // sorted positions
+    add(4 * n); add(4 * n); add(4 * n); add(4 * n);   // flags + scans
+    add(4 * (n + 1)); add(n + 1);           // octant start, bits
+    add(4 * (n + 1)); add(8 * (n + 1));     // cell octant start, keys
+    add(4 * n); add(4 * n);                 // parent, minidx
+    add(8 * hcap); add(4 * hcap);           // hash
+    add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
+    add(64);                                // counters
+    Arena* ar;
+    RS_TRY(arena_reserve(bytes, &ar));
+    uint64_t* kin = take<uint64_t>(ar, n);
+    uint64_t* kout = take<uint64_t>(ar, n);
+    int32_t* vin = take<int32_t>(ar, n);
+    int32_t* perm = take<int32_t>(ar, n);
+    float* sx = take<float>(ar, n);
+    float* sy = take<float>(ar, n);
+    float* sz = take<float>(ar, n);
+    int32_t* oflag = take<int32_t>(ar, n);
+    int32_t* cflag = take<int32_t>(ar, n);
+    int32_t* oex = take<int32_t>(ar, n);
+    int32_t* cex = take<int32_t>(ar, n);
+    int32_t* oct_start = take<int32_t>(ar, n + 1);
+    uint8_t* oct_bits = take<uint8_t>(ar, n + 1);
+    int32_t* cell_oct = take<int32_t>(ar, n + 1);
+    uint64_t* cell_key = take<uint64_t>(ar, n + 1);
+    int32_t* parent = take<int32_t>(ar, n);
+    int32_t* minidx = take<int32_t>(ar, n);
+    uint64_t* hk = take<uint64_t>(ar, hcap);
+    int32_t* hv = take<int32_t>(ar, hcap);
+    size_t stb = sort_temp_bytes(n);
+    void* stemp = arena_take(ar, stb);
+    void* ctemp = arena_take(ar, scan_temp_bytes(n));
+    int32_t* cnt = take<int32_t>(ar, 16);
+    if (!cnt) return RS_EINTERNAL;
+
+    unsigned gb = grid_for(n, BT, 1ll << 31);
+    RS_HIP(hipMemsetAsync(cnt, 0, 16 * sizeof(int32_t), st));
+    k_keys<<<gb, BT, 0, st>>>(x, y, z, n, g, kin, vin, cnt + 0);
+    RS_HIP(hipGetLastError());
+    RS_TRY(sort_pairs_u64_i32(kin, kout, vin, perm, n, g.key_bits, stemp, stb, st));
+    k_gather3<<<gb, BT, 0, st>>>(perm, x, y, z, n, sx, sy, sz);
+    k_run_flags<<<gb, BT, 0, st>>>(kout, n, oflag, cflag);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(oflag, oex, n, ctemp, cnt + 1, st));
+    RS_TRY(scan_exclusive_i32(cflag, cex, n, ctemp, cnt + 2, st));
+    int32_t* hcnt = nullptr;
+    RS_TRY(host_scratch((void**)&hcnt, 64));
+    RS_HIP(hipMemcpyAsync(hcnt, cnt, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (hcnt[0]) return RS_ERANGE;
+    int32_t n_oct = hcnt[1], n_cell = hcnt[2];
+
+    uint64_t mask = pow2_at_least((uint64_t)2 * (uint64_t)n_cell + 64) - 1;
+    RS_HIP(hipMemsetAsync(hk, 0xff, (mask + 1) * sizeof(uint64_t), st));
+    k_tables<<<gb, BT, 0, st>>>(kout, n, oflag, oex, cflag, cex, oct_start, oct_bits, cell_oct,
+                                cell_key, parent, g.autolink);
+    RS_HIP(hipGetLastError());
+    // sentinels: oct_start[n_oct] = n, cell_oct[n_cell] = n_oct
+    RS_TRY(fill_i32(oct_start + n_oct, (int32_t)n, 1, st));
+    RS_TRY(fill_i32(cell_oct + n_cell, n_oct, 1, st));
+    k_hash_insert<<<grid_for(n_cell, BT, 1ll << 31), BT, 0, st>>>(cell_key, n_cell, hk, hv, mask);
+    k_parent_init<<<gb, BT, 0, st>>>(n, oflag, oex, oct_start, parent, g.autolink);
+    RS_HIP(hipGetLastError());
+
+    LinkArgs A{oct_start, oct_bits, cell_oct, hk, hv, mask, kout, sx, sy, sz, parent, n_oct, g};
+    unsigned go = grid_for(n_oct, 256, 1ll << 31);
+    if (g.autolink)
+        k_link<true><<<go, 256, 0, st>>>(A);
+    else
+        k_link<false><<<go, 256, 0, st>>>(A);
+    RS_HIP(hipGetLastError());
+
+    k_flatten<<<gb, BT, 0, st>>>(n, parent);
+    RS_TRY(fill_i32(minidx, 0x7fffffff, n, st));
+    k_min_index<<<gb, BT, 0, st>>>(n, parent, perm, minidx);
+    unsigned long long* nroots = reinterpret_cast<unsigned long long*>(cnt + 4);
+    k_write_labels<<<gb, BT, 0, st>>>(n, parent, perm, minidx, labels, nroots);
+    RS_HIP(hipGetLastError());
+    unsigned long long* hroots = reinterpret_cast<unsigned long long*>(hcnt + 4);
+    RS_HIP(hipMemcpyAsync(hroots, nroots, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (n_groups) *n_groups = (int64_t)*hroots;
+    return RS_OK;
+}
+
+}  // namespace rs

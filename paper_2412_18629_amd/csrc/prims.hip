@@ -1,0 +1,210 @@
+// prims.hip -- device-wide building blocks: exclusive scan, key/value sort,
+// fills, and the per-device workspace.
+#include "common.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+
+static Arena g_arena[64];
+static void* g_host_scratch[64];
+static size_t g_host_scratch_bytes[64];
+
+size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
+int arena_reserve(size_t bytes, Arena** out) {
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return RS_EDEVICE;
+    Arena* a = &g_arena[dev];
+    if (a->cap < bytes) {
+        if (a->base) {
+            RS_HIP(hipFree(a->base));
+            a->base = nullptr;
+            a->cap = 0;
+        }
+        size_t want = arena_round(bytes + bytes / 8 + (1 << 20));
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return RS_ENOMEM;
+        }
+        a->base = static_cast<char*>(p);
+        a->cap = want;
+    }
+    a->off = 0;
+    *out = a;
+    return RS_OK;
+}
+
+void* arena_take(Arena* a, size_t bytes) {
+    size_t b = arena_round(bytes ? bytes : 1);
+    if (a->off + b > a->cap) return nullptr;
+    void* p = a->base + a->off;
+    a->off += b;
+    return p;
+}
+
+int host_scratch(void** out, size_t bytes) {
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (g_host_scratch_bytes[dev] < bytes) {
+        if (g_host_scratch[dev]) RS_HIP(hipHostFree(g_host_scratch[dev]));
+        g_host_scratch[dev] = nullptr;
+        g_host_scratch_bytes[dev] = 0;
+        size_t want = bytes < 4096 ? 4096 : bytes;
+        RS_HIP(hipHostMalloc(&g_host_scratch[dev], want, hipHostMallocDefault));
+        g_host_scratch_bytes[dev] = want;
+    }
+    *out = g_host_scratch[dev];
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return RS_OK;
+    k_fill_i32<<<grid_for(n, 256, 65536), 256, 0, st>>>(p, v, n);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (three-phase: tile sums, scan of sums, tile scan)
+// ---------------------------------------------------------------------------
+
+constexpr int SCAN_BT = 256;
+constexpr int SCAN_IPT = 16;
+constexpr int SCAN_TILE = SCAN_BT * SCAN_IPT;
+
+// inclusive block scan of one value per thread; returns the block total
+__device__ int32_t block_inclusive_scan(int32_t v, int32_t* lds /* [SCAN_BT/64] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_BT / 64; w++) {
+        int32_t s = lds[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    lds[SCAN_BT / 64] = total;   // scratch slot for callers that need it
+    return v + before;
+}
+
+__global__ void __launch_bounds__(SCAN_BT) k_tile_sums(const int32_t* __restrict__ in,
+                                                       int32_t* __restrict__ sums, int64_t n) {
+    __shared__ int32_t lds[SCAN_BT / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; k++) {
+        int64_t i = base + k * SCAN_BT + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int32_t inc = block_inclusive_scan(s, lds);
+    if (threadIdx.x == SCAN_BT - 1) sums[blockIdx.x] = inc;
+}
+
+// blocked scan of one tile; adds the tile offset (or 0); writes the grand
+// total when this is the last tile and total != NULL
+__global__ void __launch_bounds__(SCAN_BT) k_tile_scan(const int32_t* __restrict__ in,
+                                                       int32_t* __restrict__ out,
+                                                       const int32_t* __restrict__ offs,
+                                                       int64_t n, int32_t* __restrict__ total) {
+    __shared__ int32_t lds[SCAN_BT / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int32_t v[SCAN_IPT];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; k++) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int32_t inc = block_inclusive_scan(s, lds);
+    int32_t run = inc - s + (offs ? offs[blockIdx.x] : 0);
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; k++) {
+        int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BT - 1) *total = run;
+}
+
+size_t scan_temp_bytes(int64_t n) {
+    size_t b = 0;
+    while (n > SCAN_TILE) {
+        n = (n + SCAN_TILE - 1) / SCAN_TILE;
+        b += arena_round((size_t)n * sizeof(int32_t));
+    }
+    return b + 256;
+}
+
+int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* temp,
+                       int32_t* total_dev, hipStream_t st) {
+    if (n <= 0) {
+        if (total_dev) RS_HIP(hipMemsetAsync(total_dev, 0, sizeof(int32_t), st));
+        return RS_OK;
+    }
+    if (n <= SCAN_TILE) {
+        k_tile_scan<<<1, SCAN_BT, 0, st>>>(in, out, nullptr, n, total_dev);
+        RS_HIP(hipGetLastError());
+        return RS_OK;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int32_t* sums = static_cast<int32_t*>(temp);
+    char* rest = static_cast<char*>(temp) + arena_round((size_t)nb * sizeof(int32_t));
+    k_tile_sums<<<(unsigned)nb, SCAN_BT, 0, st>>>(in, sums, n);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(sums, sums, nb, rest, total_dev, st));
+    k_tile_scan<<<(unsigned)nb, SCAN_BT, 0, st>>>(in, out, sums, n, nullptr);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// key/value sort (LSD radix over the low `bits` bits of the key)
+// ---------------------------------------------------------------------------
+
+size_t sort_temp_bytes(int64_t n) {
+    size_t bytes = 0;
+    rocprim::radix_sort_pairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                              (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0, 64);
+    return arena_round(bytes);
+}
+
+int sort_pairs_u64_i32(const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                       int32_t* vout, int64_t n, int bits, void* temp, size_t temp_bytes,
+                       hipStream_t st) {
+    if (n <= 0) return RS_OK;
+    if (bits < 1) bits = 1;
+    if (bits > 64) bits = 64;
+    size_t tb = temp_bytes;
+    RS_HIP(rocprim::radix_sort_pairs(temp, tb, kin, kout, vin, vout, (size_t)n, 0u,
+                                     (unsigned)bits, st));
+    return RS_OK;
+}
+
+}  // namespace rs
