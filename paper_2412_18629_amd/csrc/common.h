@@ -72,6 +72,17 @@ RS_DEV int uf_find(int* par, int v) {
     return cur;
 }
 
+// read-only root walk used when flattening: it stores nothing, so parallel
+// flatteners cannot overwrite a finished entry with an intermediate ancestor
+RS_DEV int uf_root(const int* par, int v) {
+    int cur = uf_load(par, v);
+    while (cur != v) {
+        v = cur;
+        cur = uf_load(par, v);
+    }
+    return v;
+}
+
 RS_DEV void uf_unite(int* par, int a, int b) {
     int ra = uf_find(par, a), rb = uf_find(par, b);
     while (ra != rb) {
@@ -136,15 +147,16 @@ inline int hip_status(hipError_t e) {
     return e == hipErrorOutOfMemory ? RS_ENOMEM : RS_EDEVICE;
 }
 
-// Grow-only per-device workspace with a bump allocator.  A call reserves
-// its whole footprint once, then carves sub-buffers (256-byte aligned).
+// Grow-only per-device workspaces with a bump allocator.  A call reserves
+// the footprint of one phase once, then carves sub-buffers (256-byte
+// aligned).  Index 0 serves the 3D pass, 1 and 2 the 6D pass.
 struct Arena {
     char* base = nullptr;
     size_t cap = 0;
     size_t off = 0;
 };
 
-int arena_reserve(size_t bytes, Arena** out);   // resets the bump pointer
+int arena_reserve(int which, size_t bytes, Arena** out);   // resets the bump pointer
 void* arena_take(Arena* a, size_t bytes);       // NULL if the reservation is exceeded
 size_t arena_round(size_t bytes);
 

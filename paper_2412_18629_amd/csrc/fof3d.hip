@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
 __global__ void k_flatten(int64_t n, int32_t* __restrict__ parent) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
-    parent[s] = uf_find(parent, (int)s);
+    parent[s] = uf_root(parent, (int)s);
 }
 
 __global__ void k_min_index(int64_t n, const int32_t* __restrict__ parent,
@@ -331,7 +331,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
     Arena* ar;
-    RS_TRY(arena_reserve(bytes, &ar));
+    RS_TRY(arena_reserve(0, bytes, &ar));
     uint64_t* kin = take<uint64_t>(ar, n);
     uint64_t* kout = take<uint64_t>(ar, n);
     int32_t* vin = take<int32_t>(ar, n);

@@ -1,20 +1,425 @@
-// phase.hip -- hierarchical 6D phase-space FoF (placeholder until the
-// device pipeline lands).
+// phase.hip -- host orchestration of the hierarchical 6D phase-space FoF
+// (subhalo finding inside every 3D FoF halo, paper's Parallelization
+// section).
+//
+//   level 0   groups with >= min_group members become nodes; their members
+//             are packed per node (any order -- every result is a pure
+//             function of the member set)
+//   small     nodes of <= SMALL_MAX members: whole subtree in one workgroup
+//             (size-bucketed launches)
+//   large     bigger nodes: one level at a time through the tiled pipeline;
+//             their small children join the workgroup kernels
+//   output    node records are sorted by (level, smallest member index);
+//             parents and per-particle deepest nodes are remapped
+//
+// Forms: RS_BATCHED pushes all groups through each launch; RS_PLAIN walks
+// the level-0 groups one at a time (one group per launch sequence).  Both
+// run the same kernels and give identical results.
+#include <math.h>
 #include <stdlib.h>
 
-#include "common.h"
+#include <algorithm>
+#include <vector>
+
+#include "phase_common.h"
 
 namespace rs {
 
-int phase_run(const float*, const float*, const float*, const float*, const float*,
-              const float*, int64_t, float, const int32_t*, int32_t, int32_t, double, uint32_t,
-              const void*, rs_tree**, hipStream_t) {
-    return RS_ENOTIMPL;
+// ---------------------------------------------------------------------------
+// level 0
+// ---------------------------------------------------------------------------
+
+__global__ void k_p_count(const float* __restrict__ x, const float* __restrict__ y,
+                          const float* __restrict__ z, const float* __restrict__ vx,
+                          const float* __restrict__ vy, const float* __restrict__ vz,
+                          const int32_t* __restrict__ lab, int64_t n, float L,
+                          int32_t* __restrict__ cnt, int32_t* __restrict__ err) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool bad = !(x[i] >= 0.0f && x[i] < L) || !(y[i] >= 0.0f && y[i] < L) ||
+               !(z[i] >= 0.0f && z[i] < L);
+    bad |= !(fabsf(vx[i]) < 1048576.0f) || !(fabsf(vy[i]) < 1048576.0f) ||
+           !(fabsf(vz[i]) < 1048576.0f);
+    if (bad) atomicOr(err, 1);
+    int32_t l = lab[i];
+    if (l < 0 || l >= n) {
+        atomicOr(err, 2);
+        return;
+    }
+    atomicAdd(cnt + l, 1);
 }
+
+__global__ void k_p_flag(int64_t n, const int32_t* __restrict__ cnt, int32_t min_group,
+                         int32_t* __restrict__ flag) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < n) flag[r] = cnt[r] >= min_group ? 1 : 0;
+}
+
+__global__ void k_p_gsize(int64_t n, const int32_t* __restrict__ cnt,
+                          const int32_t* __restrict__ flag, const int32_t* __restrict__ gid,
+                          int32_t* __restrict__ gsize, int32_t* __restrict__ gmin,
+                          int32_t* __restrict__ gfill) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n || !flag[r]) return;
+    int32_t g = gid[r];
+    gsize[g] = cnt[r];
+    gmin[g] = 0x7fffffff;
+    gfill[g] = 0;
+}
+
+__global__ void k_p_gmin(int64_t n, const int32_t* __restrict__ lab,
+                         const int32_t* __restrict__ flag, const int32_t* __restrict__ gid,
+                         int32_t* __restrict__ gmin, int32_t* __restrict__ deepest) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t l = lab[i];
+    if (flag[l]) {
+        int32_t g = gid[l];
+        atomicMin(gmin + g, (int32_t)i);
+        deepest[i] = g;
+    } else {
+        deepest[i] = -1;
+    }
+}
+
+__global__ void k_p_fill(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
+                         const float* __restrict__ z, const float* __restrict__ vx,
+                         const float* __restrict__ vy, const float* __restrict__ vz,
+                         const int32_t* __restrict__ lab, const int32_t* __restrict__ flag,
+                         const int32_t* __restrict__ gid, const int32_t* __restrict__ goff,
+                         int32_t* __restrict__ gfill, Members A) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t l = lab[i];
+    if (!flag[l]) return;
+    int32_t g = gid[l];
+    int64_t p = (int64_t)goff[g] + atomicAdd(gfill + g, 1);
+    A.x[p] = x[i];
+    A.y[p] = y[i];
+    A.z[p] = z[i];
+    A.vx[p] = vx[i];
+    A.vy[p] = vy[i];
+    A.vz[p] = vz[i];
+    A.idx[p] = (int32_t)i;
+}
+
+// level-0 records; small groups into the bucket lists, large ones listed
+__global__ void k_p_class(int32_t G, const int32_t* __restrict__ gsize,
+                          const int32_t* __restrict__ gmin, const int32_t* __restrict__ goff,
+                          NodeRec nr, SmallItem* __restrict__ buckets, int64_t stride,
+                          int32_t* __restrict__ bcount, ChildOut* __restrict__ large,
+                          int32_t* __restrict__ nlarge) {
+    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    int32_t sz = gsize[g];
+    nr.level[g] = 0;
+    nr.minidx[g] = gmin[g];
+    nr.parent[g] = -1;
+    nr.size[g] = sz;
+    if (sz <= SMALL_MAX) {
+        int b = sz <= 64 ? 0 : sz <= 256 ? 1 : sz <= 1024 ? 2 : 3;   // small_bucket_of
+        int p = atomicAdd(bcount + b, 1);
+        buckets[b * stride + p] = SmallItem{g, 0, sz, gmin[g], (int64_t)goff[g]};
+    } else {
+        int p = atomicAdd(nlarge, 1);
+        large[p] = ChildOut{g, sz, gmin[g], 0, (int64_t)goff[g]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// output assembly
+// ---------------------------------------------------------------------------
+
+__global__ void k_o_keys(int32_t m, NodeRec nr, uint64_t* __restrict__ keys,
+                         int32_t* __restrict__ vals) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= m) return;
+    keys[s] = ((uint64_t)(uint32_t)nr.level[s] << 32) | (uint32_t)nr.minidx[s];
+    vals[s] = s;
+}
+
+__global__ void k_o_canon(int32_t m, const int32_t* __restrict__ order,
+                          int32_t* __restrict__ canon) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m) canon[order[r]] = r;
+}
+
+__global__ void k_o_nodes(int32_t m, const int32_t* __restrict__ order,
+                          const int32_t* __restrict__ canon, NodeRec nr, rs_tree t) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    int32_t s = order[r];
+    t.level[r] = nr.level[s];
+    t.min_index[r] = nr.minidx[s];
+    int32_t p = nr.parent[s];
+    t.parent[r] = p < 0 ? -1 : canon[p];
+    t.size[r] = nr.size[s];
+    t.l2[r] = nr.l2[s];
+    t.a[r] = nr.a[s];
+    t.c[r] = nr.c[s];
+    t.sx2[r] = nr.sx2[s];
+    t.sv2[r] = nr.sv2[s];
+}
+
+__global__ void k_o_deep(int64_t n, const int32_t* __restrict__ deepest,
+                         const int32_t* __restrict__ canon, int32_t* __restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t d = deepest[i];
+    out[i] = d < 0 ? -1 : canon[d];
+}
+
+// ---------------------------------------------------------------------------
 
 void tree_release(rs_tree* t) {
     if (!t) return;
+    if (t->level) (void)hipFree(t->level);
     free(t);
+}
+
+static int phase_attempt(const float* x, const float* y, const float* z, const float* vx,
+                         const float* vy, const float* vz, int64_t n, float L,
+                         const int32_t* lab, int32_t min_group, const PhaseParams& pp,
+                         uint32_t flags, int64_t cap, rs_tree** out, bool* overflow,
+                         hipStream_t st) {
+    const int BT = 256;
+    *overflow = false;
+    // ---- arena 0: level-0 tables, records, output sort ----
+    size_t bytes = 0;
+    auto add = [&](size_t b) { bytes += arena_round(b); };
+    for (int k = 0; k < 8; k++) add(4 * (size_t)n);           // cnt flag gid gsize gmin goff gfill deepest
+    for (int k = 0; k < 7; k++) add(4 * (size_t)n);           // A
+    for (int k = 0; k < 9; k++) add(4 * (size_t)cap);         // records
+    add(8 * (size_t)cap); add(8 * (size_t)cap); add(4 * (size_t)cap); add(4 * (size_t)cap);
+    add(4 * (size_t)cap);                                      // canon
+    add(sizeof(SmallItem) * 4 * (size_t)(n / 2 + 2));          // level-0 buckets
+    add(sizeof(ChildOut) * (size_t)(n / (SMALL_MAX + 1) + 2));
+    add(sort_temp_bytes(cap > n ? cap : n)); add(scan_temp_bytes(n)); add(256);
+    Arena* ar;
+    RS_TRY(arena_reserve(1, bytes, &ar));
+    int32_t* cnt = take<int32_t>(ar, n);
+    int32_t* flag = take<int32_t>(ar, n);
+    int32_t* gid = take<int32_t>(ar, n);
+    int32_t* gsize = take<int32_t>(ar, n);
+    int32_t* gmin = take<int32_t>(ar, n);
+    int32_t* goff = take<int32_t>(ar, n);
+    int32_t* gfill = take<int32_t>(ar, n);
+    int32_t* deepest = take<int32_t>(ar, n);
+    Members A;
+    A.x = take<float>(ar, n); A.y = take<float>(ar, n); A.z = take<float>(ar, n);
+    A.vx = take<float>(ar, n); A.vy = take<float>(ar, n); A.vz = take<float>(ar, n);
+    A.idx = take<int32_t>(ar, n);
+    NodeRec nr;
+    nr.level = take<int32_t>(ar, cap);
+    nr.minidx = take<int32_t>(ar, cap);
+    nr.parent = take<int32_t>(ar, cap);
+    nr.size = take<int32_t>(ar, cap);
+    nr.l2 = take<float>(ar, cap);
+    nr.a = take<float>(ar, cap);
+    nr.c = take<float>(ar, cap);
+    nr.sx2 = take<float>(ar, cap);
+    nr.sv2 = take<float>(ar, cap);
+    nr.cap = (int32_t)cap;
+    uint64_t* okin = take<uint64_t>(ar, cap);
+    uint64_t* okout = take<uint64_t>(ar, cap);
+    int32_t* ovin = take<int32_t>(ar, cap);
+    int32_t* order = take<int32_t>(ar, cap);
+    int32_t* canon = take<int32_t>(ar, cap);
+    const int64_t bstride = n / 2 + 2;
+    SmallItem* buckets = take<SmallItem>(ar, 4 * bstride);
+    ChildOut* large0 = take<ChildOut>(ar, n / (SMALL_MAX + 1) + 2);
+    size_t stb = sort_temp_bytes(cap > n ? cap : n);
+    void* stemp = arena_take(ar, stb);
+    void* ctemp = arena_take(ar, scan_temp_bytes(n));
+    int32_t* ctr = take<int32_t>(ar, 32);      // 0 err, 1 G, 2 M0, 3 count, 4 overflow, 8.. bcount, 12 nlarge
+    if (!ctr) return RS_EINTERNAL;
+    nr.count = ctr + 3;
+    nr.overflow = ctr + 4;
+    int32_t* hc = nullptr;
+    RS_TRY(host_scratch((void**)&hc, 256));
+
+    unsigned gb = grid_for(n, BT, 1ll << 31);
+    RS_HIP(hipMemsetAsync(ctr, 0, 32 * sizeof(int32_t), st));
+    RS_HIP(hipMemsetAsync(cnt, 0, 4 * (size_t)n, st));
+    k_p_count<<<gb, BT, 0, st>>>(x, y, z, vx, vy, vz, lab, n, L, cnt, ctr);
+    k_p_flag<<<gb, BT, 0, st>>>(n, cnt, min_group, flag);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(flag, gid, n, ctemp, ctr + 1, st));
+    RS_HIP(hipMemcpyAsync(hc, ctr, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (hc[0] & 2) return RS_EINVAL;
+    if (hc[0] & 1) return RS_ERANGE;
+    const int32_t G = hc[1];
+    if (G > cap) {
+        *overflow = true;
+        return RS_OK;
+    }
+    k_p_gsize<<<gb, BT, 0, st>>>(n, cnt, flag, gid, gsize, gmin, gfill);
+    k_p_gmin<<<gb, BT, 0, st>>>(n, lab, flag, gid, gmin, deepest);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(gsize, goff, G, ctemp, ctr + 2, st));
+    k_p_fill<<<gb, BT, 0, st>>>(n, x, y, z, vx, vy, vz, lab, flag, gid, goff, gfill, A);
+    k_p_class<<<grid_for(G, BT, 1ll << 31), BT, 0, st>>>(G, gsize, gmin, goff, nr, buckets,
+                                                          bstride, ctr + 8, large0, ctr + 12);
+    RS_HIP(hipGetLastError());
+    RS_TRY(fill_i32(nr.count, G, 1, st));
+    RS_HIP(hipMemcpyAsync(hc, ctr, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    const int32_t nlarge = hc[12];
+    int32_t bcnt[4] = {hc[8], hc[9], hc[10], hc[11]};
+    std::vector<ChildOut> large(nlarge);
+    if (nlarge > 0) {
+        RS_HIP(hipMemcpyAsync(large.data(), large0, sizeof(ChildOut) * nlarge,
+                              hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+        std::sort(large.begin(), large.end(),
+                  [](const ChildOut& a, const ChildOut& b) { return a.slot < b.slot; });
+    }
+    int64_t mlarge = 0;
+    for (auto& c : large) mlarge += c.size;
+
+    // ---- large-node work space (arena 2) ----
+    LargeWork lw;
+    if (nlarge > 0) {
+        Arena* ar2;
+        RS_TRY(arena_reserve(2, large_work_bytes(mlarge), &ar2));
+        RS_TRY(large_work_carve(ar2, mlarge, &lw));
+    }
+
+    if (flags == RS_PLAIN) {
+        // one level-0 group per launch sequence, in slot order
+        std::vector<SmallItem> hs;
+        for (int b = 0; b < 4; b++) {
+            size_t o = hs.size();
+            hs.resize(o + bcnt[b]);
+            if (bcnt[b] > 0)
+                RS_HIP(hipMemcpyAsync(hs.data() + o, buckets + b * bstride,
+                                      sizeof(SmallItem) * bcnt[b], hipMemcpyDeviceToHost, st));
+        }
+        RS_HIP(hipStreamSynchronize(st));
+        std::sort(hs.begin(), hs.end(),
+                  [](const SmallItem& a, const SmallItem& b) { return a.slot < b.slot; });
+        SmallItem* one = buckets;   // reuse: the host copy is complete
+        size_t si = 0, li = 0;
+        while (si < hs.size() || li < large.size()) {
+            bool take_small =
+                li >= large.size() || (si < hs.size() && hs[si].slot < large[li].slot);
+            if (take_small) {
+                RS_HIP(hipMemcpyAsync(one, &hs[si], sizeof(SmallItem), hipMemcpyHostToDevice, st));
+                RS_TRY(run_small_bucket(small_bucket_of(hs[si].size), one, 1, A, nr, pp, deepest,
+                                        st));
+                RS_HIP(hipStreamSynchronize(st));
+                si++;
+            } else {
+                std::vector<ChildOut> cur{large[li]}, nxt;
+                const Members* in = &A;
+                while (!cur.empty()) {
+                    RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, st));
+                    cur.swap(nxt);
+                    in = &lw.N;
+                }
+                li++;
+            }
+        }
+    } else {
+        for (int b = 3; b >= 0; b--)
+            RS_TRY(run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, st));
+        std::vector<ChildOut> cur = large, nxt;
+        const Members* in = &A;
+        while (!cur.empty()) {
+            RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, st));
+            cur.swap(nxt);
+            in = &lw.N;
+        }
+    }
+
+    // ---- output ----
+    RS_HIP(hipMemcpyAsync(hc, ctr + 3, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (hc[1]) {
+        *overflow = true;
+        return RS_OK;
+    }
+    const int32_t m = hc[0];
+    if (m > 0) {
+        k_o_keys<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, nr, okin, ovin);
+        RS_HIP(hipGetLastError());
+        RS_TRY(sort_pairs_u64_i32(okin, okout, ovin, order, m, 48, stemp, stb,
+                                  st));
+        k_o_canon<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, canon);
+        RS_HIP(hipGetLastError());
+    }
+    size_t nodes_bytes = arena_round(4 * (size_t)(m > 0 ? m : 1));
+    size_t total = 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1));
+    rs_tree* t = (rs_tree*)calloc(1, sizeof(rs_tree));
+    if (!t) return RS_ENOMEM;
+    char* blk = nullptr;
+    hipError_t e = hipMalloc((void**)&blk, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free(t);
+        return RS_ENOMEM;
+    }
+    t->n_nodes = m;
+    t->n_particles = n;
+    t->level = (int32_t*)(blk + 0 * nodes_bytes);
+    t->min_index = (int32_t*)(blk + 1 * nodes_bytes);
+    t->parent = (int32_t*)(blk + 2 * nodes_bytes);
+    t->size = (int32_t*)(blk + 3 * nodes_bytes);
+    t->l2 = (float*)(blk + 4 * nodes_bytes);
+    t->a = (float*)(blk + 5 * nodes_bytes);
+    t->c = (float*)(blk + 6 * nodes_bytes);
+    t->sx2 = (float*)(blk + 7 * nodes_bytes);
+    t->sv2 = (float*)(blk + 8 * nodes_bytes);
+    t->deepest = (int32_t*)(blk + 9 * nodes_bytes);
+    int rc = RS_OK;
+    if (m > 0) k_o_nodes<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, canon, nr, *t);
+    if (n > 0) k_o_deep<<<gb, BT, 0, st>>>(n, deepest, canon, t->deepest);
+    if (hipGetLastError() != hipSuccess) rc = RS_EDEVICE;
+    int32_t last_level = -1;
+    if (rc == RS_OK && m > 0) {
+        if (hipMemcpyAsync(&last_level, t->level + (m - 1), sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = RS_EDEVICE;
+    }
+    if (rc == RS_OK && hipStreamSynchronize(st) != hipSuccess) rc = RS_EDEVICE;
+    if (rc != RS_OK) {
+        tree_release(t);
+        return rc;
+    }
+    t->n_levels = last_level + 1;
+    *out = t;
+    return RS_OK;
+}
+
+int phase_run(const float* x, const float* y, const float* z, const float* vx,
+              const float* vy, const float* vz, int64_t n, float L, const int32_t* labels,
+              int32_t min_group, int32_t min_sub, double f, uint32_t flags, const void* model,
+              rs_tree** out, hipStream_t st) {
+    (void)model;
+    if (flags == RS_LEARNED) return RS_ENOTIMPL;
+    PhaseParams pp;
+    pp.L = L;
+    pp.h = 0.5f * L;
+    pp.LQ = (int64_t)rint((double)L * 1048576.0);
+    pp.min_sub = min_sub;
+    pp.f_ppm = llround(f * 1e6);
+    int64_t cap = n / (min_group > 1 ? min_group : 1) + 4 * (n / (min_sub > 1 ? min_sub : 1)) / 3 +
+                  1024;
+    if (cap > 0x7ffffff0ll) cap = 0x7ffffff0ll;
+    for (int attempt = 0; attempt < 8; attempt++) {
+        bool overflow = false;
+        rs_tree* t = nullptr;
+        RS_TRY(phase_attempt(x, y, z, vx, vy, vz, n, L, labels, min_group, pp, flags, cap, &t,
+                             &overflow, st));
+        if (!overflow) {
+            *out = t;
+            return RS_OK;
+        }
+        if (cap >= 0x7ffffff0ll) return RS_EINTERNAL;
+        cap = cap * 2 > 0x7ffffff0ll ? 0x7ffffff0ll : cap * 2;
+    }
+    return RS_EINTERNAL;
 }
 
 }  // namespace rs

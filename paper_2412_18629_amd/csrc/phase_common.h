@@ -1,0 +1,251 @@
+// phase_common.h -- shared pieces of the 6D phase-space FoF kernels.
+//
+// Node normalisation (dispersions) uses exact integer moments, so any
+// summation order -- wave shuffles, LDS atomics, global atomics -- gives the
+// same result:
+//   Q = rint(x * 2^20) (fp64), relative to the node's smallest-index member
+//   in the nearest periodic image (integer arithmetic), W = rint(v * 2^10);
+//   per axis S1 = sum(delta), S2 = sum(delta^2) (128-bit);
+//   V = sum_axes (N*S2 - S1^2) = N^2 * sigma^2 in quantum units;
+//   a = fl32(((double)N*(double)N / f64(V)) * 2^40), c likewise with 2^20,
+//   and 1 when V = 0.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace rs {
+
+constexpr int SMALL_MAX = 2048;   // largest node handled inside one workgroup
+
+struct PhaseParams {
+    float L, h;
+    int64_t LQ;        // rint(L * 2^20)
+    int32_t min_sub;
+    int64_t f_ppm;     // llround(f * 1e6)
+};
+
+// node record store (slots allocated by atomics, canonical order at the end)
+struct NodeRec {
+    int32_t *level, *minidx, *parent, *size;
+    float *l2, *a, *c, *sx2, *sv2;
+    int32_t* count;     // device counter of used slots
+    int32_t cap;
+    int32_t* overflow;  // set when a slot beyond cap was requested
+};
+
+// SoA member buffer
+struct Members {
+    float *x, *y, *z, *vx, *vy, *vz;
+    int32_t* idx;
+};
+
+// a node whose whole subtree is split inside one workgroup
+struct SmallItem {
+    int32_t slot, level, size, refidx;   // refidx: smallest member particle index
+    int64_t off;                         // first member in its member buffer
+};
+
+// a large node handed to the next level of the large-node pipeline
+struct ChildOut {
+    int32_t slot, size, minidx, level;
+    int64_t off;                         // first member in its member buffer
+};
+
+struct LNode;
+struct LItem;
+struct LParam;
+struct LCounters;
+
+// device buffers of the large-node pipeline, sized by the level-0 total of
+// large-node members (which bounds every later level)
+struct LargeWork {
+    int64_t cap_m, cap_nodes, cap_items, cap_tiles, cap_supers, cap_small;
+    Members T, S, N;
+    uint64_t *kin, *kout;
+    int32_t *src, *perm, *mnode, *par, *cnt, *cslot, *cfill;
+    int64_t* coff;
+    int8_t* cclass;
+    unsigned long long* mpk;
+    float* d2;
+    LNode* nodes;
+    LItem* items;
+    LParam* prm;
+    unsigned long long* gacc;
+    uint32_t* gext;
+    int32_t* ghist;
+    int32_t *tile_node, *super_node;
+    float *tbox, *sbox;
+    LCounters* ctr;
+    SmallItem* small_items;
+    SmallItem* buckets;
+    int32_t* bcount;
+    ChildOut* large_out;
+    void* sort_temp;
+    size_t sort_temp_bytes;
+};
+
+size_t large_work_bytes(int64_t m);
+int large_work_carve(Arena* ar, int64_t m, LargeWork* w);
+int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Members& mb,
+                       const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
+                       hipStream_t st);
+int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
+                const float* X, const float* Y, const float* Z, const PhaseParams& pp,
+                const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
+                hipStream_t st);
+int run_small_bucket(int b, const SmallItem* items, int n_items, const Members& mb,
+                     const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
+                     hipStream_t st);
+int small_bucket_of(int size);
+
+RS_DEV int64_t select_rank(int64_t n, int64_t ppm) {
+    int64_t k = (n * ppm + 999999) / 1000000;
+    return k < 1 ? 1 : (k > n ? n : k);
+}
+
+RS_DEV int64_t quant_pos(float x) { return (int64_t)rint((double)x * 1048576.0); }
+RS_DEV int64_t quant_vel(float v) { return (int64_t)rint((double)v * 1024.0); }
+
+// 18 words: s1[0..5] (pos xyz, vel xyz; two's complement), then s2 lo/hi
+// pairs for the same six quantities.
+struct Moments {
+    uint64_t s1[6];
+    u128 s2[6];
+};
+
+RS_DEV void mom_zero(Moments& m) {
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+        m.s1[q] = 0;
+        m.s2[q] = 0;
+    }
+}
+
+RS_DEV void mom_add(Moments& m, float px, float py, float pz, float vx, float vy, float vz,
+                    const int64_t qref[3], int64_t LQ) {
+    float p[3] = {px, py, pz};
+    float v[3] = {vx, vy, vz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+        int64_t d = quant_pos(p[ax]) - qref[ax];
+        if (2 * d > LQ) d -= LQ;
+        else if (2 * d <= -LQ) d += LQ;
+        m.s1[ax] += (uint64_t)d;
+        m.s2[ax] += (u128)(uint64_t)(d * d);
+        int64_t w = quant_vel(v[ax]);
+        m.s1[3 + ax] += (uint64_t)w;
+        m.s2[3 + ax] += (u128)(uint64_t)(w * w);
+    }
+}
+
+RS_DEV uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask, 64);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// sum over the 64 lanes (every lane ends with the total)
+RS_DEV void mom_wave_reduce(Moments& m) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            m.s1[q] += shfl_xor_u64(m.s1[q], off);
+            uint64_t lo = (uint64_t)m.s2[q], hi = (uint64_t)(m.s2[q] >> 64);
+            uint64_t olo = shfl_xor_u64(lo, off), ohi = shfl_xor_u64(hi, off);
+            m.s2[q] += ((u128)ohi << 64) | (u128)olo;
+        }
+    }
+}
+
+// add one wave's moments into an 18-word accumulator (LDS or global)
+RS_DEV void acc_add128(unsigned long long* lo_p, unsigned long long* hi_p, u128 v) {
+    unsigned long long lo = (unsigned long long)(uint64_t)v;
+    unsigned long long hi = (unsigned long long)(uint64_t)(v >> 64);
+    unsigned long long old = atomicAdd(lo_p, lo);
+    unsigned long long carry = (old + lo) < old ? 1ull : 0ull;
+    atomicAdd(hi_p, hi + carry);
+}
+
+RS_DEV void mom_accumulate(unsigned long long* acc, const Moments& m) {
+#pragma unroll
+    for (int q = 0; q < 6; q++) atomicAdd(acc + q, (unsigned long long)m.s1[q]);
+#pragma unroll
+    for (int q = 0; q < 6; q++) acc_add128(acc + 6 + 2 * q, acc + 7 + 2 * q, m.s2[q]);
+}
+
+struct Norm {
+    float a, c, sx2, sv2;
+    double mean[6];   // mean position offset (from ref, fp64) and mean velocity
+};
+
+RS_DEV Norm mom_finalize(const unsigned long long* acc, int64_t n) {
+    i128 Vx = 0, Vv = 0;
+    Norm r;
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+        int64_t s1 = (int64_t)acc[q];
+        u128 s2 = ((u128)acc[7 + 2 * q] << 64) | (u128)acc[6 + 2 * q];
+        i128 t = (i128)n * (i128)s2 - (i128)s1 * (i128)s1;
+        if (q < 3) Vx += t; else Vv += t;
+        r.mean[q] = (double)s1 / (double)n * (q < 3 ? 9.5367431640625e-07 : 9.765625e-4);
+    }
+    double nn = (double)n * (double)n;
+    double vx = i128_to_f64(Vx), vv = i128_to_f64(Vv);
+    r.a = (Vx == 0) ? 1.0f : (float)((nn / vx) * 1099511627776.0);
+    r.c = (Vv == 0) ? 1.0f : (float)((nn / vv) * 1048576.0);
+    r.sx2 = (float)((vx / nn) * 9.094947017729282e-13);
+    r.sv2 = (float)((vv / nn) * 9.5367431640625e-07);
+    return r;
+}
+
+// pair metric for one candidate, with or without the periodic shift
+template <bool WRAP>
+RS_DEV float phase_d2(float xi, float yi, float zi, float ui, float vi, float wi, float xj,
+                      float yj, float zj, float uj, float vj, float wj, float a, float c,
+                      float L, float h) {
+    float Dx = WRAP ? pos_d2_wrap(xi, yi, zi, xj, yj, zj, L, h)
+                    : pos_d2_nowrap(xi, yi, zi, xj, yj, zj);
+    float Dv = sum_sq3(ui - uj, vi - vj, wi - wj);
+    return metric(a, Dx, c, Dv);
+}
+
+// lock-free union-find in LDS (same invariant as the global version)
+RS_DEV int lds_find(int* par, int v) {
+    int cur = __hip_atomic_load(par + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == v) return v;
+    int prev = v, next;
+    while (cur > (next = __hip_atomic_load(par + cur, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP))) {
+        __hip_atomic_store(par + prev, next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        prev = cur;
+        cur = next;
+    }
+    return cur;
+}
+
+// read-only root walk, for flattening: stores nothing but the final root, so
+// concurrent flatteners never overwrite a root entry with an older ancestor
+RS_DEV int lds_root(const int* par, int v) {
+    int cur = __hip_atomic_load(par + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (cur != v) {
+        v = cur;
+        cur = __hip_atomic_load(par + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return v;
+}
+
+RS_DEV void lds_unite(int* par, int a, int b) {
+    int ra = lds_find(par, a), rb = lds_find(par, b);
+    while (ra != rb) {
+        if (ra > rb) { int t = ra; ra = rb; rb = t; }
+        int old = atomicCAS(par + rb, rb, ra);
+        if (old == rb) return;
+        rb = lds_find(par, old);
+        ra = lds_find(par, ra);
+    }
+}
+
+}  // namespace rs

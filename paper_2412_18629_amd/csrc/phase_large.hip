@@ -1,0 +1,857 @@
+// phase_large.hip -- one recursion level of the 6D split for nodes too large
+// for a single workgroup's LDS (more than SMALL_MAX members).
+//
+// All large nodes of a level are processed together:
+//   moments   per (node, chunk) work items -> global 128-bit accumulators
+//   keys      6D Morton code of the normalised, centred coordinates (a
+//             monotone log-like squash per axis); node rank in the top bits
+//   sort      key/index radix sort -> members of a node are contiguous and
+//             6D-local; 64 consecutive members form a tile, 64 tiles a
+//             super-tile; each has a 6D bounding box (positions unwrapped
+//             around the node's reference member, raw velocities)
+//   NN        one wavefront per tile; candidate tiles are visited outward
+//             from the own super-tile and skipped when an exact lower bound
+//             of d^2 over the whole box cannot beat the lane's best
+//   select    per-node 4-pass radix select of the k-th smallest d^2
+//   link      one wavefront per tile against later tiles, skipped when the
+//             box lower bound exceeds l^2; global lock-free union-find
+//   children  components of >= min_sub members (not the whole node): small
+//             ones go to the workgroup-subtree kernel, large ones to the
+//             next level
+// Bounding-box culling only removes pairs whose computed d^2 provably cannot
+// matter (slack covers every fp32 rounding of the coordinates and the
+// metric); nodes spanning more than a quarter box per axis are not culled.
+#include "phase_common.h"
+
+namespace rs {
+
+struct LNode {              // one large node of the current level
+    int32_t slot, size, minidx, level;
+    int64_t in_off;         // first member in the input buffer
+    int64_t t_off;          // first member in tile order
+    int32_t tile0, ntile, super0, nsuper;
+};
+
+struct LItem {              // (node, chunk) work item
+    int32_t v, len;
+    int64_t in_start, t_start;
+};
+
+struct LParam {
+    float a, c, sa, sc;
+    float rx, ry, rz;       // reference member position
+    float cx, cy, cz;       // mean position (for the sort key only)
+    float cu, cv, cw;       // mean velocity (sort key only)
+    int32_t nowrap, cull;
+    uint32_t pf, pm;        // radix-select prefix and mask
+    int32_t kk;             // remaining rank
+    float l2;
+};
+
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_lmom(const LItem* __restrict__ items, const LNode* __restrict__ nodes, Members in,
+       const float* __restrict__ X, const float* __restrict__ Y, const float* __restrict__ Z,
+       PhaseParams pp, unsigned long long* __restrict__ gacc, uint32_t* __restrict__ gext) {
+    __shared__ unsigned long long acc[18];
+    __shared__ uint32_t ext[6];
+    const LItem it = items[blockIdx.x];
+    const LNode nd = nodes[it.v];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 18) acc[tid] = 0;
+    if (tid < 3) ext[tid] = 0xffffffffu;
+    else if (tid < 6) ext[tid] = 0;
+    __syncthreads();
+    int64_t qref[3] = {quant_pos(X[nd.minidx]), quant_pos(Y[nd.minidx]), quant_pos(Z[nd.minidx])};
+    Moments mo;
+    mom_zero(mo);
+    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0, 0, 0};
+    for (int j = tid; j < it.len; j += 256) {
+        int64_t g = it.in_start + j;
+        float p[3] = {in.x[g], in.y[g], in.z[g]};
+        mom_add(mo, p[0], p[1], p[2], in.vx[g], in.vy[g], in.vz[g], qref, pp.LQ);
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            uint32_t b = __float_as_uint(p[ax]);
+            mn[ax] = b < mn[ax] ? b : mn[ax];
+            mx[ax] = b > mx[ax] ? b : mx[ax];
+        }
+    }
+    if (wave * 64 < it.len) {
+        mom_wave_reduce(mo);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+            for (int ax = 0; ax < 3; ax++) {
+                uint32_t o1 = (uint32_t)__shfl_xor((int)mn[ax], off, 64);
+                uint32_t o2 = (uint32_t)__shfl_xor((int)mx[ax], off, 64);
+                mn[ax] = o1 < mn[ax] ? o1 : mn[ax];
+                mx[ax] = o2 > mx[ax] ? o2 : mx[ax];
+            }
+        if (lane == 0) {
+            mom_accumulate(acc, mo);
+            for (int ax = 0; ax < 3; ax++) {
+                atomicMin(ext + ax, mn[ax]);
+                atomicMax(ext + 3 + ax, mx[ax]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long* g = gacc + 18 * (int64_t)it.v;
+        for (int q = 0; q < 6; q++) atomicAdd(g + q, acc[q]);
+        for (int q = 0; q < 6; q++) {
+            u128 v = ((u128)acc[7 + 2 * q] << 64) | (u128)acc[6 + 2 * q];
+            acc_add128(g + 6 + 2 * q, g + 7 + 2 * q, v);
+        }
+        for (int ax = 0; ax < 3; ax++) {
+            atomicMin(gext + 6 * it.v + ax, ext[ax]);
+            atomicMax(gext + 6 * it.v + 3 + ax, ext[3 + ax]);
+        }
+    }
+}
+
+__global__ void k_lnorm(int nv, const LNode* __restrict__ nodes,
+                        const unsigned long long* __restrict__ gacc,
+                        const uint32_t* __restrict__ gext, const float* __restrict__ X,
+                        const float* __restrict__ Y, const float* __restrict__ Z,
+                        PhaseParams pp, NodeRec nr, LParam* __restrict__ prm) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const LNode nd = nodes[v];
+    Norm nm = mom_finalize(gacc + 18 * (int64_t)v, nd.size);
+    LParam P;
+    P.a = nm.a;
+    P.c = nm.c;
+    P.sa = sqrtf(nm.a);
+    P.sc = sqrtf(nm.c);
+    P.rx = X[nd.minidx];
+    P.ry = Y[nd.minidx];
+    P.rz = Z[nd.minidx];
+    P.cx = (float)((double)P.rx + nm.mean[0]);
+    P.cy = (float)((double)P.ry + nm.mean[1]);
+    P.cz = (float)((double)P.rz + nm.mean[2]);
+    P.cu = (float)nm.mean[3];
+    P.cv = (float)nm.mean[4];
+    P.cw = (float)nm.mean[5];
+    bool nowrap = true;
+    for (int ax = 0; ax < 3; ax++) {
+        float e = __uint_as_float(gext[6 * v + 3 + ax]) - __uint_as_float(gext[6 * v + ax]);
+        nowrap = nowrap && (e <= pp.h);
+    }
+    P.nowrap = nowrap ? 1 : 0;
+    P.cull = 0;
+    P.pf = 0;
+    P.pm = 0;
+    P.kk = (int32_t)select_rank(nd.size, pp.f_ppm);
+    P.l2 = 0.0f;
+    prm[v] = P;
+    nr.a[nd.slot] = nm.a;
+    nr.c[nd.slot] = nm.c;
+    nr.sx2[nd.slot] = nm.sx2;
+    nr.sv2[nd.slot] = nm.sv2;
+}
+
+// squash a normalised coordinate into [0, 128): finer near the centre
+RS_DEV uint32_t squash7(float u) {
+    float t = copysignf(log1pf(8.0f * fabsf(u)) * 0.28853901f, u);   // 1/ln(33)
+    t = fminf(fmaxf(t, -1.0f), 1.0f);
+    int q = (int)((t + 1.0f) * 63.999f);
+    return (uint32_t)(q < 0 ? 0 : (q > 127 ? 127 : q));
+}
+
+RS_DEV uint64_t morton6(const uint32_t q[6]) {
+    uint64_t k = 0;
+#pragma unroll
+    for (int b = 6; b >= 0; b--)
+#pragma unroll
+        for (int d = 0; d < 6; d++) k = (k << 1) | ((q[d] >> b) & 1u);
+    return k;
+}
+
+__global__ void __launch_bounds__(256)
+k_lkeys(const LItem* __restrict__ items, Members in, const LParam* __restrict__ prm,
+        PhaseParams pp, uint64_t* __restrict__ keys, int32_t* __restrict__ src) {
+    const LItem it = items[blockIdx.x];
+    const LParam P = prm[it.v];
+    for (int j = threadIdx.x; j < it.len; j += 256) {
+        int64_t g = it.in_start + j;
+        uint32_t q[6];
+        q[0] = squash7(min_image(in.x[g] - P.cx, pp.L, pp.h) * P.sa);
+        q[1] = squash7(min_image(in.y[g] - P.cy, pp.L, pp.h) * P.sa);
+        q[2] = squash7(min_image(in.z[g] - P.cz, pp.L, pp.h) * P.sa);
+        q[3] = squash7((in.vx[g] - P.cu) * P.sc);
+        q[4] = squash7((in.vy[g] - P.cv) * P.sc);
+        q[5] = squash7((in.vz[g] - P.cw) * P.sc);
+        int64_t t = it.t_start + j;
+        keys[t] = ((uint64_t)it.v << 42) | morton6(q);
+        src[t] = (int32_t)g;
+    }
+}
+
+__global__ void k_lgather(int64_t m, const int32_t* __restrict__ perm,
+                          const uint64_t* __restrict__ skeys, Members in, Members out,
+                          int32_t* __restrict__ mnode) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int32_t s = perm[t];
+    out.x[t] = in.x[s];
+    out.y[t] = in.y[s];
+    out.z[t] = in.z[s];
+    out.vx[t] = in.vx[s];
+    out.vy[t] = in.vy[s];
+    out.vz[t] = in.vz[s];
+    out.idx[t] = in.idx[s];
+    mnode[t] = (int32_t)(skeys[t] >> 42);
+}
+
+RS_DEV void tile_range(const LNode& nd, int t, int64_t* ts, int64_t* te) {
+    int64_t s = nd.t_off + 64ll * (t - nd.tile0);
+    int64_t e = s + 64;
+    int64_t end = nd.t_off + nd.size;
+    *ts = s;
+    *te = e < end ? e : end;
+}
+
+RS_DEV float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+RS_DEV float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// tile boxes: [lo wx wy wz u v w, hi wx wy wz u v w]
+__global__ void __launch_bounds__(64)
+k_ltbox(const int32_t* __restrict__ tile_node, const LNode* __restrict__ nodes, Members T,
+        const LParam* __restrict__ prm, PhaseParams pp, float* __restrict__ tbox) {
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int v = tile_node[t];
+    const LNode nd = nodes[v];
+    const LParam P = prm[v];
+    int64_t ts, te;
+    tile_range(nd, t, &ts, &te);
+    int64_t m = ts + lane;
+    bool ok = m < te;
+    float c[6];
+    if (ok) {
+        c[0] = min_image(T.x[m] - P.rx, pp.L, pp.h);
+        c[1] = min_image(T.y[m] - P.ry, pp.L, pp.h);
+        c[2] = min_image(T.z[m] - P.rz, pp.L, pp.h);
+        c[3] = T.vx[m];
+        c[4] = T.vy[m];
+        c[5] = T.vz[m];
+    }
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        float lo = wave_min(ok ? c[d] : __builtin_huge_valf());
+        float hi = wave_max(ok ? c[d] : -__builtin_huge_valf());
+        if (lane == 0) {
+            tbox[12 * (int64_t)t + d] = lo;
+            tbox[12 * (int64_t)t + 6 + d] = hi;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_lsbox(const int32_t* __restrict__ super_node, const LNode* __restrict__ nodes,
+        const float* __restrict__ tbox, float* __restrict__ sbox) {
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const LNode nd = nodes[super_node[s]];
+    int t0 = nd.tile0 + 64 * (s - nd.super0);
+    int t1 = t0 + 64;
+    if (t1 > nd.tile0 + nd.ntile) t1 = nd.tile0 + nd.ntile;
+    int t = t0 + lane;
+    bool ok = t < t1;
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        float lo = wave_min(ok ? tbox[12 * (int64_t)t + d] : __builtin_huge_valf());
+        float hi = wave_max(ok ? tbox[12 * (int64_t)t + 6 + d] : -__builtin_huge_valf());
+        if (lane == 0) {
+            sbox[12 * (int64_t)s + d] = lo;
+            sbox[12 * (int64_t)s + 6 + d] = hi;
+        }
+    }
+}
+
+// culling is allowed when every pair's min-image difference is the
+// difference of the unwrapped coordinates: extent below a quarter box
+__global__ void k_lcull(int nv, const LNode* __restrict__ nodes, const float* __restrict__ sbox,
+                        PhaseParams pp, LParam* __restrict__ prm) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const LNode nd = nodes[v];
+    float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+    for (int s = nd.super0; s < nd.super0 + nd.nsuper; s++)
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fminf(lo[d], sbox[12 * (int64_t)s + d]);
+            hi[d] = fmaxf(hi[d], sbox[12 * (int64_t)s + 6 + d]);
+        }
+    bool ok = true;
+    for (int d = 0; d < 3; d++) ok = ok && (hi[d] - lo[d] <= 0.5f * pp.h);
+    prm[v].cull = ok ? 1 : 0;
+}
+
+// Exact lower bound of the computed d^2 between a member (w: unwrapped
+// position, u: velocity) and any member inside a box.  Position gaps lose an
+// absolute slack covering the rounding of x - x_ref, of the pair difference
+// and of the image shift (<= 3 * 2^-24 * L); velocity gaps a relative 2^-20;
+// the result a relative 1e-5 for the roundings of the bound itself and of
+// the metric.
+RS_DEV float box_lb(const float* __restrict__ b, const float w[3], const float u[3], float a,
+                    float c, float slack) {
+    float sp = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        float g = fmaxf(fmaxf(b[d] - w[d], w[d] - b[6 + d]), 0.0f);
+        g = fmaxf(g - slack, 0.0f);
+        sp += g * g;
+        float h = fmaxf(fmaxf(b[3 + d] - u[d], u[d] - b[9 + d]), 0.0f) * 0.99999905f;
+        sv += h * h;
+    }
+    return (a * sp + c * sv) * 0.99999f;
+}
+
+struct LKArgs {
+    const int32_t* tile_node;
+    const LNode* nodes;
+    const LParam* prm;
+    const float* tbox;
+    const float* sbox;
+    Members T;
+    PhaseParams pp;
+    float slack;
+};
+
+template <bool WRAP>
+RS_DEV void tile_nn(const float* cx, const float* cy, const float* cz, const float* cu,
+                    const float* cv, const float* cw, int cnt, int self, float xi, float yi,
+                    float zi, float ui, float vi, float wi, float a, float c, float L, float h,
+                    float& best) {
+    for (int j = 0; j < cnt; j++) {
+        float d = phase_d2<WRAP>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j],
+                                 cw[j], a, c, L, h);
+        best = (j != self && d < best) ? d : best;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_lnn(LKArgs A, float* __restrict__ d2out) {
+    __shared__ float cx[64], cy[64], cz[64], cu[64], cv[64], cw[64];
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int v = A.tile_node[t];
+    const LNode nd = A.nodes[v];
+    const LParam P = A.prm[v];
+    const Members& T = A.T;
+    int64_t ts, te;
+    tile_range(nd, t, &ts, &te);
+    const int64_t m = ts + lane;
+    const bool valid = m < te;
+    const int64_t mm = valid ? m : ts;
+    const float xi = T.x[mm], yi = T.y[mm], zi = T.z[mm];
+    const float ui = T.vx[mm], vi = T.vy[mm], wi = T.vz[mm];
+    const float w[3] = {min_image(xi - P.rx, A.pp.L, A.pp.h), min_image(yi - P.ry, A.pp.L, A.pp.h),
+                        min_image(zi - P.rz, A.pp.L, A.pp.h)};
+    const float u[3] = {ui, vi, wi};
+    float best = __builtin_huge_valf();
+
+    auto stage = [&](int64_t s0, int64_t s1) {
+        __syncthreads();
+        int64_t q = s0 + lane;
+        if (q < s1) {
+            cx[lane] = T.x[q]; cy[lane] = T.y[q]; cz[lane] = T.z[q];
+            cu[lane] = T.vx[q]; cv[lane] = T.vy[q]; cw[lane] = T.vz[q];
+        }
+        __syncthreads();
+        return (int)(s1 - s0);
+    };
+    auto scan = [&](int cnt, int self) {
+        if (P.nowrap)
+            tile_nn<false>(cx, cy, cz, cu, cv, cw, cnt, self, xi, yi, zi, ui, vi, wi, P.a, P.c,
+                           A.pp.L, A.pp.h, best);
+        else
+            tile_nn<true>(cx, cy, cz, cu, cv, cw, cnt, self, xi, yi, zi, ui, vi, wi, P.a, P.c,
+                          A.pp.L, A.pp.h, best);
+    };
+
+    scan(stage(ts, te), lane);
+    const int sown = nd.super0 + (t - nd.tile0) / 64;
+    const int send = nd.super0 + nd.nsuper;
+    int span = sown - nd.super0;
+    if (send - 1 - sown > span) span = send - 1 - sown;
+    for (int d = 0; d <= span; d++) {
+        for (int side = 0; side < 2; side++) {
+            if (d == 0 && side == 1) continue;
+            int s = side == 0 ? sown + d : sown - d;
+            if (s < nd.super0 || s >= send) continue;
+            if (P.cull) {
+                bool need = valid && box_lb(A.sbox + 12 * (int64_t)s, w, u, P.a, P.c, A.slack) < best;
+                if (!__any(need)) continue;
+            }
+            int u0 = nd.tile0 + 64 * (s - nd.super0);
+            int u1 = u0 + 64;
+            if (u1 > nd.tile0 + nd.ntile) u1 = nd.tile0 + nd.ntile;
+            for (int tu = u0; tu < u1; tu++) {
+                if (tu == t) continue;
+                if (P.cull) {
+                    bool need =
+                        valid && box_lb(A.tbox + 12 * (int64_t)tu, w, u, P.a, P.c, A.slack) < best;
+                    if (!__any(need)) continue;
+                }
+                int64_t q0, q1;
+                tile_range(nd, tu, &q0, &q1);
+                scan(stage(q0, q1), -1);
+            }
+        }
+    }
+    if (valid) d2out[m] = best;
+}
+
+// ---------------------------------------------------------------------------
+// per-node radix select over the d^2 bit patterns
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_lhist(const LItem* __restrict__ items, const float* __restrict__ d2,
+        const LParam* __restrict__ prm, int shift, int32_t* __restrict__ ghist) {
+    __shared__ int32_t hist[256];
+    const LItem it = items[blockIdx.x];
+    const LParam P = prm[it.v];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < it.len; j += 256) {
+        uint32_t u = __float_as_uint(d2[it.t_start + j]);
+        if ((u & P.pm) == P.pf) atomicAdd(hist + ((u >> shift) & 255u), 1);
+    }
+    __syncthreads();
+    int h = hist[threadIdx.x];
+    if (h) atomicAdd(ghist + 256 * (int64_t)it.v + threadIdx.x, h);
+}
+
+__global__ void __launch_bounds__(64)
+k_lpick(const int32_t* __restrict__ ghist, int shift, LParam* __restrict__ prm,
+        const LNode* __restrict__ nodes, NodeRec nr, int last) {
+    const int v = blockIdx.x, lane = threadIdx.x;
+    const int32_t* hh = ghist + 256 * (int64_t)v;
+    int h0 = hh[4 * lane], h1 = hh[4 * lane + 1], h2 = hh[4 * lane + 2], h3 = hh[4 * lane + 3];
+    int tot = h0 + h1 + h2 + h3, inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    int before = inc - tot;
+    int kk = prm[v].kk;
+    if (before < kk && kk <= inc) {
+        int k2 = kk - before, b = 4 * lane;
+        if (k2 > h0) { k2 -= h0; b++;
+            if (k2 > h1) { k2 -= h1; b++;
+                if (k2 > h2) { k2 -= h2; b++; } } }
+        uint32_t pf = prm[v].pf | ((uint32_t)b << shift);
+        prm[v].pf = pf;
+        prm[v].pm |= 255u << shift;
+        prm[v].kk = k2;
+        if (last) {
+            prm[v].l2 = __uint_as_float(pf);
+            nr.l2[nodes[v].slot] = __uint_as_float(pf);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// linking within l
+// ---------------------------------------------------------------------------
+
+template <bool WRAP>
+RS_DEV void tile_link(const float* cx, const float* cy, const float* cz, const float* cu,
+                      const float* cv, const float* cw, int cnt, int jmin, int64_t q0,
+                      bool act, int64_t m, float xi, float yi, float zi, float ui, float vi,
+                      float wi, float a, float c, float l2, float L, float h, int32_t* par) {
+    for (int j = jmin; j < cnt; j++) {
+        float d = phase_d2<WRAP>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j],
+                                 cw[j], a, c, L, h);
+        if (act && d <= l2) uf_unite(par, (int)m, (int)(q0 + j));
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_llink(LKArgs A, const float* __restrict__ d2, int32_t* __restrict__ par) {
+    __shared__ float cx[64], cy[64], cz[64], cu[64], cv[64], cw[64];
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int v = A.tile_node[t];
+    const LNode nd = A.nodes[v];
+    const LParam P = A.prm[v];
+    const Members& T = A.T;
+    int64_t ts, te;
+    tile_range(nd, t, &ts, &te);
+    const int64_t m = ts + lane;
+    const bool valid = m < te;
+    const int64_t mm = valid ? m : ts;
+    const bool act = valid && d2[mm] <= P.l2;
+    if (!__any(act)) return;
+    const float xi = T.x[mm], yi = T.y[mm], zi = T.z[mm];
+    const float ui = T.vx[mm], vi = T.vy[mm], wi = T.vz[mm];
+    const float w[3] = {min_image(xi - P.rx, A.pp.L, A.pp.h), min_image(yi - P.ry, A.pp.L, A.pp.h),
+                        min_image(zi - P.rz, A.pp.L, A.pp.h)};
+    const float u[3] = {ui, vi, wi};
+
+    auto stage = [&](int64_t s0, int64_t s1) {
+        __syncthreads();
+        int64_t q = s0 + lane;
+        if (q < s1) {
+            cx[lane] = T.x[q]; cy[lane] = T.y[q]; cz[lane] = T.z[q];
+            cu[lane] = T.vx[q]; cv[lane] = T.vy[q]; cw[lane] = T.vz[q];
+        }
+        __syncthreads();
+        return (int)(s1 - s0);
+    };
+    auto run = [&](int cnt, int jmin, int64_t q0) {
+        if (P.nowrap)
+            tile_link<false>(cx, cy, cz, cu, cv, cw, cnt, jmin, q0, act, m, xi, yi, zi, ui, vi,
+                             wi, P.a, P.c, P.l2, A.pp.L, A.pp.h, par);
+        else
+            tile_link<true>(cx, cy, cz, cu, cv, cw, cnt, jmin, q0, act, m, xi, yi, zi, ui, vi, wi,
+                            P.a, P.c, P.l2, A.pp.L, A.pp.h, par);
+    };
+
+    // own tile: pairs (lane, j) with j > lane
+    {
+        int cnt = stage(ts, te);
+        for (int j = 0; j < cnt; j++) {
+            float d = P.nowrap
+                ? phase_d2<false>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j], cw[j],
+                                  P.a, P.c, A.pp.L, A.pp.h)
+                : phase_d2<true>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j], cw[j],
+                                 P.a, P.c, A.pp.L, A.pp.h);
+            if (act && j > lane && d <= P.l2) uf_unite(par, (int)m, (int)(ts + j));
+        }
+    }
+    const int sown = nd.super0 + (t - nd.tile0) / 64;
+    const int send = nd.super0 + nd.nsuper;
+    for (int s = sown; s < send; s++) {
+        if (P.cull) {
+            bool need = act && !(box_lb(A.sbox + 12 * (int64_t)s, w, u, P.a, P.c, A.slack) > P.l2);
+            if (!__any(need)) continue;
+        }
+        int u0 = nd.tile0 + 64 * (s - nd.super0);
+        int u1 = u0 + 64;
+        if (u1 > nd.tile0 + nd.ntile) u1 = nd.tile0 + nd.ntile;
+        if (u0 <= t) u0 = t + 1;
+        for (int tu = u0; tu < u1; tu++) {
+            if (P.cull) {
+                bool need =
+                    act && !(box_lb(A.tbox + 12 * (int64_t)tu, w, u, P.a, P.c, A.slack) > P.l2);
+                if (!__any(need)) continue;
+            }
+            int64_t q0, q1;
+            tile_range(nd, tu, &q0, &q1);
+            run(stage(q0, q1), 0, q0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// components and children
+// ---------------------------------------------------------------------------
+
+__global__ void k_liota(int64_t m, int32_t* __restrict__ par) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < m) par[t] = (int32_t)t;
+}
+
+__global__ void k_lflat(int64_t m, int32_t* __restrict__ par, int32_t* __restrict__ cnt,
+                        unsigned long long* __restrict__ mpk) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    par[t] = uf_root(par, (int)t);
+    cnt[t] = 0;
+    mpk[t] = ~0ull;
+}
+
+__global__ void k_lstat(int64_t m, const int32_t* __restrict__ par,
+                        const int32_t* __restrict__ idx, int32_t* __restrict__ cnt,
+                        unsigned long long* __restrict__ mpk) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int32_t r = par[t];
+    atomicAdd(cnt + r, 1);
+    atomicMin(mpk + r, ((unsigned long long)(uint32_t)idx[t] << 32) | (uint32_t)t);
+}
+
+struct LCounters {
+    int32_t n_small, n_large;
+    unsigned long long tot_small, tot_large;
+};
+
+__global__ void k_lchild(int64_t m, const int32_t* __restrict__ par,
+                         const int32_t* __restrict__ cnt,
+                         const unsigned long long* __restrict__ mpk,
+                         const int32_t* __restrict__ mnode, const LNode* __restrict__ nodes,
+                         PhaseParams pp, NodeRec nr, int32_t* __restrict__ cslot,
+                         int64_t* __restrict__ coff, int32_t* __restrict__ cfill,
+                         int8_t* __restrict__ cclass, LCounters* __restrict__ ctr,
+                         SmallItem* __restrict__ small_items, ChildOut* __restrict__ large_out) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    if (par[t] != (int32_t)t) return;
+    const LNode nd = nodes[mnode[t]];
+    int c = cnt[t];
+    cslot[t] = -1;
+    if (c < pp.min_sub || c >= nd.size) return;
+    int slot = atomicAdd(nr.count, 1);
+    if (slot >= nr.cap) {
+        atomicOr(nr.overflow, 1);
+        return;
+    }
+    int minidx = (int)(mpk[t] >> 32);
+    nr.level[slot] = nd.level + 1;
+    nr.minidx[slot] = minidx;
+    nr.parent[slot] = nd.slot;
+    nr.size[slot] = c;
+    int64_t off;
+    if (c <= SMALL_MAX) {
+        off = (int64_t)atomicAdd(&ctr->tot_small, (unsigned long long)c);
+        int i = atomicAdd(&ctr->n_small, 1);
+        small_items[i] = SmallItem{slot, nd.level + 1, c, minidx, off};
+        cclass[t] = 0;
+    } else {
+        off = (int64_t)atomicAdd(&ctr->tot_large, (unsigned long long)c);
+        int i = atomicAdd(&ctr->n_large, 1);
+        large_out[i] = ChildOut{slot, c, minidx, nd.level + 1, off};
+        cclass[t] = 1;
+    }
+    coff[t] = off;
+    cfill[t] = 0;
+    cslot[t] = slot;
+}
+
+__global__ void k_lscatter(int64_t m, const int32_t* __restrict__ par, Members T,
+                           const int32_t* __restrict__ cslot, const int64_t* __restrict__ coff,
+                           int32_t* __restrict__ cfill, const int8_t* __restrict__ cclass,
+                           Members S, Members N, int32_t* __restrict__ deepest) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int32_t r = par[t];
+    int32_t s = cslot[r];
+    if (s < 0) return;
+    int64_t pos = coff[r] + atomicAdd(cfill + r, 1);
+    Members D = cclass[r] ? N : S;
+    D.x[pos] = T.x[t];
+    D.y[pos] = T.y[t];
+    D.z[pos] = T.z[t];
+    D.vx[pos] = T.vx[t];
+    D.vy[pos] = T.vy[t];
+    D.vz[pos] = T.vz[t];
+    D.idx[pos] = T.idx[t];
+    deepest[T.idx[t]] = s;
+}
+
+__global__ void k_lext_init(int nv, uint32_t* __restrict__ gext) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * nv) gext[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
+}
+
+__global__ void k_bucket(const SmallItem* __restrict__ in, int n, SmallItem* __restrict__ out,
+                         int64_t stride, int32_t* __restrict__ bcount) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    SmallItem it = in[i];
+    int b = it.size <= 64 ? 0 : it.size <= 256 ? 1 : it.size <= 1024 ? 2 : 3;   // small_bucket_of
+    int p = atomicAdd(bcount + b, 1);
+    out[b * stride + p] = it;
+}
+
+// ---------------------------------------------------------------------------
+// host side of one level
+// ---------------------------------------------------------------------------
+
+size_t large_work_bytes(int64_t m) {
+    int64_t nodes = m / (SMALL_MAX + 1) + 2;
+    int64_t items = m / 4096 + nodes + 2;
+    int64_t tiles = m / 64 + nodes + 2;
+    int64_t supers = tiles / 64 + nodes + 2;
+    int64_t small = m / 2 + 2;
+    size_t b = 0;
+    auto add = [&](size_t x) { b += arena_round(x); };
+    for (int k = 0; k < 3 * 7; k++) add(4 * m);                 // T, S, N
+    add(8 * m); add(8 * m);                                     // keys
+    for (int k = 0; k < 7; k++) add(4 * m);                     // src..cfill
+    add(8 * m); add(m); add(8 * m); add(4 * m);                 // coff, cclass, mpk, d2
+    add(sizeof(LNode) * nodes); add(sizeof(LItem) * items); add(sizeof(LParam) * nodes);
+    add(8 * 18 * nodes); add(4 * 6 * nodes); add(4 * 256 * nodes);
+    add(4 * tiles); add(4 * supers); add(4 * 12 * tiles); add(4 * 12 * supers);
+    add(sizeof(LCounters)); add(sizeof(SmallItem) * small); add(sizeof(SmallItem) * 4 * small);
+    add(64); add(sizeof(ChildOut) * nodes);
+    add(sort_temp_bytes(m));
+    return b + 4096;
+}
+
+int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
+    w->cap_m = m;
+    w->cap_nodes = m / (SMALL_MAX + 1) + 2;
+    w->cap_items = m / 4096 + w->cap_nodes + 2;
+    w->cap_tiles = m / 64 + w->cap_nodes + 2;
+    w->cap_supers = w->cap_tiles / 64 + w->cap_nodes + 2;
+    w->cap_small = m / 2 + 2;
+    Members* bufs[3] = {&w->T, &w->S, &w->N};
+    for (Members* b : bufs) {
+        b->x = take<float>(ar, m); b->y = take<float>(ar, m); b->z = take<float>(ar, m);
+        b->vx = take<float>(ar, m); b->vy = take<float>(ar, m); b->vz = take<float>(ar, m);
+        b->idx = take<int32_t>(ar, m);
+    }
+    w->kin = take<uint64_t>(ar, m);
+    w->kout = take<uint64_t>(ar, m);
+    w->src = take<int32_t>(ar, m);
+    w->perm = take<int32_t>(ar, m);
+    w->mnode = take<int32_t>(ar, m);
+    w->par = take<int32_t>(ar, m);
+    w->cnt = take<int32_t>(ar, m);
+    w->cslot = take<int32_t>(ar, m);
+    w->cfill = take<int32_t>(ar, m);
+    w->coff = take<int64_t>(ar, m);
+    w->cclass = take<int8_t>(ar, m);
+    w->mpk = take<unsigned long long>(ar, m);
+    w->d2 = take<float>(ar, m);
+    w->nodes = take<LNode>(ar, w->cap_nodes);
+    w->items = take<LItem>(ar, w->cap_items);
+    w->prm = take<LParam>(ar, w->cap_nodes);
+    w->gacc = take<unsigned long long>(ar, 18 * w->cap_nodes);
+    w->gext = take<uint32_t>(ar, 6 * w->cap_nodes);
+    w->ghist = take<int32_t>(ar, 256 * w->cap_nodes);
+    w->tile_node = take<int32_t>(ar, w->cap_tiles);
+    w->super_node = take<int32_t>(ar, w->cap_supers);
+    w->tbox = take<float>(ar, 12 * w->cap_tiles);
+    w->sbox = take<float>(ar, 12 * w->cap_supers);
+    w->ctr = take<LCounters>(ar, 1);
+    w->small_items = take<SmallItem>(ar, w->cap_small);
+    w->buckets = take<SmallItem>(ar, 4 * w->cap_small);
+    w->bcount = take<int32_t>(ar, 16);
+    w->large_out = take<ChildOut>(ar, w->cap_nodes);
+    w->sort_temp_bytes = sort_temp_bytes(m);
+    w->sort_temp = arena_take(ar, w->sort_temp_bytes);
+    return w->sort_temp ? RS_OK : RS_EINTERNAL;
+}
+
+// Launches the small-subtree kernels over a device list of small items whose
+// members live in `mb`.
+int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Members& mb,
+                       const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
+                       hipStream_t st) {
+    if (n <= 0) return RS_OK;
+    RS_HIP(hipMemsetAsync(w->bcount, 0, 16 * sizeof(int32_t), st));
+    k_bucket<<<grid_for(n, 256, 1ll << 31), 256, 0, st>>>(items, n, w->buckets, w->cap_small,
+                                                          w->bcount);
+    RS_HIP(hipGetLastError());
+    int32_t* hb = nullptr;
+    RS_TRY(host_scratch((void**)&hb, 64));
+    RS_HIP(hipMemcpyAsync(hb, w->bcount, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    int cnts[4] = {hb[0], hb[1], hb[2], hb[3]};
+    for (int b = 3; b >= 0; b--)
+        RS_TRY(run_small_bucket(b, w->buckets + b * w->cap_small, cnts[b], mb, nr, pp, deepest, st));
+    return RS_OK;
+}
+
+// One level over the large nodes `hn` (host copies) whose members live in
+// `in`.  Appends the next level's large nodes to `next` (offsets into w->N).
+int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
+                const float* X, const float* Y, const float* Z, const PhaseParams& pp,
+                const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
+                hipStream_t st) {
+    const int nv = (int)hn.size();
+    std::vector<LNode> nodes(nv);
+    std::vector<LItem> items;
+    std::vector<int32_t> tile_node, super_node;
+    int64_t toff = 0;
+    int32_t tiles = 0, supers = 0;
+    for (int v = 0; v < nv; v++) {
+        LNode& nd = nodes[v];
+        nd.slot = hn[v].slot;
+        nd.size = hn[v].size;
+        nd.minidx = hn[v].minidx;
+        nd.level = hn[v].level;
+        nd.in_off = hn[v].off;
+        nd.t_off = toff;
+        nd.ntile = (nd.size + 63) / 64;
+        nd.nsuper = (nd.ntile + 63) / 64;
+        nd.tile0 = tiles;
+        nd.super0 = supers;
+        for (int64_t c = 0; c < nd.size; c += 4096) {
+            int len = (int)(nd.size - c < 4096 ? nd.size - c : 4096);
+            items.push_back(LItem{v, len, nd.in_off + c, toff + c});
+        }
+        for (int k = 0; k < nd.ntile; k++) tile_node.push_back(v);
+        for (int k = 0; k < nd.nsuper; k++) super_node.push_back(v);
+        tiles += nd.ntile;
+        supers += nd.nsuper;
+        toff += nd.size;
+    }
+    const int64_t M = toff;
+    if (nv > w->cap_nodes || (int64_t)items.size() > w->cap_items || tiles > w->cap_tiles ||
+        supers > w->cap_supers || M > w->cap_m)
+        return RS_EINTERNAL;
+    const int ni = (int)items.size();
+    RS_HIP(hipMemcpyAsync(w->nodes, nodes.data(), sizeof(LNode) * nv, hipMemcpyHostToDevice, st));
+    RS_HIP(hipMemcpyAsync(w->items, items.data(), sizeof(LItem) * ni, hipMemcpyHostToDevice, st));
+    RS_HIP(hipMemcpyAsync(w->tile_node, tile_node.data(), 4 * (size_t)tiles,
+                          hipMemcpyHostToDevice, st));
+    RS_HIP(hipMemcpyAsync(w->super_node, super_node.data(), 4 * (size_t)supers,
+                          hipMemcpyHostToDevice, st));
+    RS_HIP(hipMemsetAsync(w->gacc, 0, 8 * 18 * (size_t)nv, st));
+    k_lext_init<<<grid_for(6 * nv, 256), 256, 0, st>>>(nv, w->gext);
+    const int BT = 256;
+    unsigned gm = grid_for(M, BT, 1ll << 31);
+    k_lmom<<<ni, 256, 0, st>>>(w->items, w->nodes, in, X, Y, Z, pp, w->gacc, w->gext);
+    k_lnorm<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->gacc, w->gext, X, Y, Z, pp, nr,
+                                             w->prm);
+    k_lkeys<<<ni, 256, 0, st>>>(w->items, in, w->prm, pp, w->kin, w->src);
+    RS_HIP(hipGetLastError());
+    int vbits = 1;
+    while ((1 << vbits) < nv) vbits++;
+    RS_TRY(sort_pairs_u64_i32(w->kin, w->kout, w->src, w->perm, M, 42 + vbits, w->sort_temp,
+                              w->sort_temp_bytes, st));
+    k_lgather<<<gm, BT, 0, st>>>(M, w->perm, w->kout, in, w->T, w->mnode);
+    k_ltbox<<<tiles, 64, 0, st>>>(w->tile_node, w->nodes, w->T, w->prm, pp, w->tbox);
+    k_lsbox<<<supers, 64, 0, st>>>(w->super_node, w->nodes, w->tbox, w->sbox);
+    k_lcull<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->sbox, pp, w->prm);
+    RS_HIP(hipGetLastError());
+    LKArgs A{w->tile_node, w->nodes, w->prm, w->tbox, w->sbox, w->T, pp,
+             8.0f * pp.L * 5.9604645e-08f};
+    k_lnn<<<tiles, 64, 0, st>>>(A, w->d2);
+    RS_HIP(hipGetLastError());
+    for (int pass = 0; pass < 4; pass++) {
+        int shift = 24 - 8 * pass;
+        RS_HIP(hipMemsetAsync(w->ghist, 0, 4 * 256 * (size_t)nv, st));
+        k_lhist<<<ni, 256, 0, st>>>(w->items, w->d2, w->prm, shift, w->ghist);
+        k_lpick<<<nv, 64, 0, st>>>(w->ghist, shift, w->prm, w->nodes, nr, pass == 3);
+        RS_HIP(hipGetLastError());
+    }
+    k_liota<<<gm, BT, 0, st>>>(M, w->par);
+    k_llink<<<tiles, 64, 0, st>>>(A, w->d2, w->par);
+    k_lflat<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk);
+    k_lstat<<<gm, BT, 0, st>>>(M, w->par, w->T.idx, w->cnt, w->mpk);
+    RS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(LCounters), st));
+    k_lchild<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk, w->mnode, w->nodes, pp, nr, w->cslot,
+                                w->coff, w->cfill, w->cclass, w->ctr, w->small_items,
+                                w->large_out);
+    k_lscatter<<<gm, BT, 0, st>>>(M, w->par, w->T, w->cslot, w->coff, w->cfill, w->cclass, w->S,
+                                  w->N, deepest);
+    RS_HIP(hipGetLastError());
+    LCounters hc;
+    RS_HIP(hipMemcpyAsync(&hc, w->ctr, sizeof(LCounters), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    RS_TRY(launch_small_items(w, w->small_items, hc.n_small, w->S, nr, pp, deepest, st));
+    next->resize(hc.n_large);
+    if (hc.n_large > 0) {
+        RS_HIP(hipMemcpyAsync(next->data(), w->large_out, sizeof(ChildOut) * hc.n_large,
+                              hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+    }
+    return RS_OK;
+}
+
+}  // namespace rs

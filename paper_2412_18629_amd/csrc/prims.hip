@@ -10,17 +10,17 @@ namespace rs {
 // workspace
 // ---------------------------------------------------------------------------
 
-static Arena g_arena[64];
+static Arena g_arena[64][4];
 static void* g_host_scratch[64];
 static size_t g_host_scratch_bytes[64];
 
 size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 
-int arena_reserve(size_t bytes, Arena** out) {
+int arena_reserve(int which, size_t bytes, Arena** out) {
     int dev = 0;
     RS_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return RS_EDEVICE;
-    Arena* a = &g_arena[dev];
+    if (dev < 0 || dev >= 64 || which < 0 || which >= 4) return RS_EDEVICE;
+    Arena* a = &g_arena[dev][which];
     if (a->cap < bytes) {
         if (a->base) {
             RS_HIP(hipFree(a->base));

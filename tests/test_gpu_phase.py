@@ -1,0 +1,154 @@
+"""GPU parity of rs_phase_fof_batch against the CPU oracle.
+
+Every node field (level, smallest member index, parent, size, l^2, a, c,
+sigma^2) and the per-particle deepest node must be bit-identical to the
+oracle's, for both execution forms.  The workloads include groups above the
+workgroup limit of 2048 members, so the tiled large-node pipeline runs too.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2412_18629_amd as rs
+from paper_2412_18629_amd import synth
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2")
+
+
+def _dev(arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=F32)).cuda() for a in arrs]
+
+
+def compare(got, ref):
+    n = len(ref["level"])
+    assert len(got["level"]) == n, (len(got["level"]), n)
+    for k in FIELDS:
+        g = got[k].cpu().numpy()
+        r = ref[k]
+        if not np.array_equal(g, r):
+            bad = np.nonzero(g != r)[0]
+            raise AssertionError(f"field {k}: {bad.size} mismatches, first at {bad[:5]}: "
+                                 f"gpu {g[bad[:5]]} oracle {r[bad[:5]]}")
+    assert np.array_equal(got["deepest"].cpu().numpy(), ref["deepest"])
+
+
+def run_both(arrs, box, labels_np, flags=rs.RS_BATCHED, **kw):
+    t = _dev(arrs)
+    lab = torch.from_numpy(np.ascontiguousarray(labels_np, dtype=np.int32)).cuda()
+    got = rs.rs_phase_fof_batch(*t, box, lab, flags=flags, **kw)
+    ref = oracle.phase_fof(*arrs, box, labels_np, **kw)
+    return got, ref
+
+
+def _workload(cfg, seed):
+    arrs = [a.numpy() for a in synth.generate(cfg, seed)]
+    lab = oracle.fof3d(*arrs[:3], cfg.box, cfg.link_len)
+    return arrs, lab
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_parity_32cubed(seed):
+    cfg = synth.CONFIGS["c32"]
+    arrs, lab = _workload(cfg, seed)
+    got, ref = run_both(arrs, cfg.box, lab)
+    assert (ref["size"] > 2048).any()          # large-node path exercised
+    compare(got, ref)
+
+
+def test_parity_32cubed_plain_form():
+    cfg = synth.CONFIGS["c32"]
+    arrs, lab = _workload(cfg, 0)
+    got, ref = run_both(arrs, cfg.box, lab, flags=rs.RS_PLAIN)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("n,seed", [(5000, 3), (120000, 4), (400000, 5)])
+def test_parity_scaled(n, seed):
+    cfg = synth.scaled(synth.CONFIGS["c32"], n)
+    arrs, lab = _workload(cfg, seed)
+    got, ref = run_both(arrs, cfg.box, lab)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("min_group,min_sub,f", [(2, 2, 0.7), (20, 5, 0.5), (10, 10, 1.0),
+                                                 (50, 30, 0.9)])
+def test_parameters(min_group, min_sub, f):
+    cfg = synth.scaled(synth.CONFIGS["c32"], 60000)
+    arrs, lab = _workload(cfg, 6)
+    got, ref = run_both(arrs, cfg.box, lab, min_group=min_group, min_sub=min_sub, f=f)
+    compare(got, ref)
+
+
+def _single(pos, vel, box, **kw):
+    pos = np.asarray(pos, F32); vel = np.asarray(vel, F32)
+    arrs = [pos[:, 0], pos[:, 1], pos[:, 2], vel[:, 0], vel[:, 1], vel[:, 2]]
+    lab = np.zeros(pos.shape[0], np.int32)
+    return run_both(arrs, box, lab, **kw)
+
+
+def test_degenerate_nodes():
+    rng = np.random.default_rng(2)
+    # all coincident (sigma = 0, l = 0, leaf)
+    compare(*_single(np.full((30, 3), 2.5), np.full((30, 3), 7.0), 10.0))
+    # duplicates
+    base = 3.0 + rng.uniform(0, 0.1, (12, 3)); vb = rng.normal(0, 50, (12, 3))
+    compare(*_single(np.concatenate([base[:8], base[:8], base[8:]]),
+                     np.concatenate([vb[:8], vb[:8], vb[8:]]), 10.0))
+    # a line lattice with zero velocities (ties at l)
+    n, s = 40, 0.125
+    pos = np.zeros((n, 3)); pos[:, 0] = 1.0 + s * np.arange(n); pos[:, 1] = 2; pos[:, 2] = 3
+    compare(*_single(pos, np.zeros((n, 3)), 16.0))
+    # two particles, min sizes 2
+    compare(*_single([[1, 1, 1], [1.5, 1, 1]], [[0, 0, 0], [1, 2, 3]], 8.0, min_group=2,
+                     min_sub=2))
+    # clumps separated in velocity, straddling the periodic faces
+    m = 700
+    pos = np.concatenate([np.mod(rng.normal(0, 0.05, (m, 3)), 20.0) for _ in range(3)])
+    vel = np.concatenate([rng.normal(0, 10.0, (m, 3)) + [4000.0 * k, 0, 0] for k in range(3)])
+    compare(*_single(pos, vel, 20.0))
+    # one large node (> 2048 members) across the faces
+    pos = np.mod(rng.normal(0, 0.3, (6000, 3)), 20.0)
+    vel = rng.normal(0, 200.0, (6000, 3))
+    compare(*_single(pos, vel, 20.0))
+
+
+def test_no_groups_and_empty():
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, 10, (100, 3)); vel = rng.normal(0, 1, (100, 3))
+    arrs = [pos[:, k] for k in range(3)] + [vel[:, k] for k in range(3)]
+    lab = np.arange(100, dtype=np.int32)           # all singletons
+    got, ref = run_both(arrs, 10.0, lab)
+    assert len(ref["level"]) == 0
+    compare(got, ref)
+    z = [np.zeros(0, F32)] * 6
+    got = rs.rs_phase_fof_batch(*_dev(z), 10.0, torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert got["level"].numel() == 0 and got["n_levels"] == 0
+
+
+def test_bad_labels_and_range():
+    pos = np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.5]], F32)
+    vel = np.zeros((2, 3), F32)
+    t = _dev([pos[:, 0], pos[:, 1], pos[:, 2], vel[:, 0], vel[:, 1], vel[:, 2]])
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_phase_fof_batch(*t, 10.0, torch.tensor([0, 5], dtype=torch.int32, device="cuda"))
+    assert e.value.status == rs.RS_EINVAL
+    t[2][1] = 11.0
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_phase_fof_batch(*t, 10.0, torch.tensor([0, 0], dtype=torch.int32, device="cuda"),
+                              min_group=2, min_sub=2)
+    assert e.value.status == rs.RS_ERANGE
+
+
+def test_repeat_identical_and_forms_agree():
+    cfg = synth.scaled(synth.CONFIGS["c32"], 150000)
+    arrs, lab_np = _workload(cfg, 7)
+    t = _dev(arrs)
+    lab = torch.from_numpy(lab_np).cuda()
+    a = rs.rs_phase_fof_batch(*t, cfg.box, lab)
+    b = rs.rs_phase_fof_batch(*t, cfg.box, lab)
+    c = rs.rs_phase_fof_batch(*t, cfg.box, lab, flags=rs.RS_PLAIN)
+    for k in FIELDS + ("deepest",):
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
