@@ -1,0 +1,144 @@
+"""Benchmark: particles/s through the 3D + hierarchical 6D FoF hot path.
+
+One step = rs_fof3d over the whole box, then rs_phase_fof_batch over every
+3D group, on the 512^3 synthetic workload (inputs resident in HBM before the
+timed region).  Prints one JSON line with the throughput, the roofline of the
+dominant kernel (HIP events recorded by the library on its launch stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form batched|plain]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+import paper_2412_18629_amd as rs  # noqa: E402
+from paper_2412_18629_amd import synth  # noqa: E402
+
+METRIC = "particles/s through 3D+6D FoF at 512³ (labels == oracle); learned vs plain speedup"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per work unit of each instrumented kernel
+KERNEL_BYTES = {
+    "fof3d_link": 16.0,        # 12 B sorted position in, 4 B parent out, per particle
+    "phase_large_nn": 28.0,    # 24 B position+velocity in, 4 B d^2 out, per member
+    "phase_large_link": 32.0,  # 24 B pos+vel + 4 B d^2 in, 4 B parent out, per member
+    "phase_small": 32.0,       # 28 B member record in, 4 B deepest out, per member
+}
+
+
+def workload_description(cfg):
+    return (f"{cfg.name}: {cfg.n} particles (512^3) in a periodic {cfg.box:g} Mpc/h box, "
+            f"{cfg.n_hosts} NFW hosts of {cfg.m_lo:g}-{cfg.m_hi:g} particles (dn/dM ~ M^{cfg.slope}) "
+            f"with 0-{cfg.n_sub_max} subhaloes, {cfg.bg_frac:.0%} uniform background; 3D FoF "
+            f"b={cfg.b} (ll={cfg.link_len:.6g}), 6D FoF f={cfg.f}, min group/subgroup "
+            f"{cfg.min_group}/{cfg.min_sub}; seed 0")
+
+
+def one_step(arrs, cfg, flags, labels):
+    x, y, z, vx, vy, vz = arrs
+    rs.rs_fof3d(x, y, z, cfg.box, cfg.link_len, labels=labels)
+    return rs.rs_phase_fof_batch(x, y, z, vx, vy, vz, cfg.box, labels, cfg.min_group,
+                                 cfg.min_sub, cfg.f, flags=flags)
+
+
+def cpu_baseline(arrs, cfg, target=400000):
+    """The oracle (single-threaded C) on a cubic sub-box of the same data,
+    run as a periodic box of its own: 3D FoF then the 6D hierarchy."""
+    import oracle
+    side = cfg.box * (target / cfg.n) ** (1.0 / 3.0)
+    x, y, z = arrs[0], arrs[1], arrs[2]
+    m = (x < side) & (y < side) & (z < side)
+    sub = [a[m].cpu().numpy() for a in arrs]
+    n = sub[0].size
+    t0 = time.perf_counter()
+    lab = oracle.fof3d(sub[0], sub[1], sub[2], side, cfg.link_len)
+    t1 = time.perf_counter()
+    oracle.phase_fof(*sub, side, lab, cfg.min_group, cfg.min_sub, cfg.f)
+    t2 = time.perf_counter()
+    return {"value": n / (t2 - t0), "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{n} particles inside the sub-box [0,{side:.2f})^3 Mpc/h of the same "
+                       f"workload, run as a periodic box of that side; 3D FoF "
+                       f"{t1 - t0:.2f} s + 6D {t2 - t1:.2f} s single-threaded")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c512")
+    ap.add_argument("--form", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method's hot path runs on a single MI355X; "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+    if not torch.cuda.is_available():
+        print("no HIP device visible", file=sys.stderr)
+        return 2
+    rs.load()
+    cfg = synth.CONFIGS[args.config]
+    flags = {"batched": rs.RS_BATCHED, "plain": rs.RS_PLAIN}[args.form]
+    dev = torch.device("cuda:0")
+    arrs = synth.generate(cfg, 0, device=dev)
+    labels = torch.empty(cfg.n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        one_step(arrs, cfg, flags, labels)
+    torch.cuda.synchronize()
+
+    rs.rs_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tree = one_step(arrs, cfg, flags, labels)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {k: rs.rs_profile_get(k) for k in KERNEL_BYTES}
+    rs.rs_profile_enable(False)
+
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = cfg.n / (ms / 1000.0)
+    n_groups = int((tree["level"] == 0).sum().item())
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot_ms, launches, units = prof[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    bytes_per_launch = KERNEL_BYTES[dom] * units / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    line = {
+        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload_description(cfg), "form": args.form,
+                   "groups": n_groups, "nodes": int(tree["level"].numel()),
+                   "levels": tree["n_levels"],
+                   "groups_per_s": n_groups / (ms / 1000.0),
+                   "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "launches": launches,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(arrs, cfg)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -130,6 +130,18 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z,
                        uint32_t flags, const void* model, rs_tree** out,
                        void* stream);
 
+/*
+ * Instrumentation (not part of the method).  While enabled, the library
+ * records HIP events on the launching stream around its main kernels
+ * ("fof3d_link", "phase_small", "phase_large_nn", "phase_large_link") and
+ * accumulates their elapsed time, launch count and processed work units
+ * (particles or node members).  rs_profile_enable(0) clears the records.
+ * rs_profile_get synchronises on the recorded events; unknown names report
+ * zeros.  Returns RS_OK, or RS_EINVAL for NULL arguments.
+ */
+int rs_profile_enable(int on);
+int rs_profile_get(const char* name, double* total_ms, int64_t* launches, double* units);
+
 /* Releases an rs_tree* (struct and device arrays).  NULL is a no-op. */
 void rs_free(void* p);
 

@@ -18,7 +18,8 @@ RS_OK, RS_EINVAL, RS_ERANGE, RS_ENOMEM, RS_EDEVICE, RS_EINTERNAL, RS_ENOTIMPL = 
     0, -1, -2, -3, -4, -5, -6)
 RS_PLAIN, RS_BATCHED, RS_LEARNED = 0, 1, 2
 
-EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version")
+EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
+            "rs_profile_enable", "rs_profile_get")
 
 
 class RsError(RuntimeError):
@@ -61,6 +62,11 @@ def load():
     lib.rs_strerror.restype = ctypes.c_char_p
     lib.rs_version.argtypes = []
     lib.rs_version.restype = ctypes.c_char_p
+    lib.rs_profile_enable.argtypes = [ctypes.c_int]
+    lib.rs_profile_enable.restype = ctypes.c_int
+    lib.rs_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64),
+                                   ctypes.POINTER(f64)]
+    lib.rs_profile_get.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -165,3 +171,17 @@ def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_s
     finally:
         lib.rs_free(out)
     return res
+
+
+def rs_profile_enable(on: bool = True) -> None:
+    """Record HIP events around the library's main kernels (instrumentation)."""
+    load().rs_profile_enable(1 if on else 0)
+
+
+def rs_profile_get(name: str):
+    """(total_ms, launches, units) recorded for one instrumented kernel."""
+    ms, n, u = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
+    rc = load().rs_profile_get(name.encode(), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u))
+    if rc != RS_OK:
+        raise RsError(rc, "rs_profile_get")
+    return ms.value, int(n.value), u.value

@@ -95,6 +95,24 @@ RS_DEV void uf_unite(int* par, int a, int b) {
 }
 
 // ---------------------------------------------------------------------------
+// wave-level aggregation of atomics on clustered keys: lanes holding the same
+// key elect a leader, so a run of equal keys costs one atomic, not one per
+// lane.  Every lane of the wavefront must call these (ballots).
+// ---------------------------------------------------------------------------
+
+RS_DEV uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
+RS_DEV unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, o, 64);
+        unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), o, 64);
+        unsigned long long w = ((unsigned long long)hi << 32) | lo;
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
 // exact 128-bit helpers
 // ---------------------------------------------------------------------------
 
@@ -174,6 +192,12 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
     if (g > cap) g = cap;
     return (unsigned)g;
 }
+
+// Optional per-kernel timing with HIP events recorded on the launching
+// stream around instrumented launches (off unless enabled by the caller).
+// `units` counts the work items a launch processed (members, particles).
+void prof_begin(const char* name, hipStream_t st);
+void prof_end(const char* name, hipStream_t st, double units);
 
 // device-wide primitives (prims.hip)
 size_t scan_temp_bytes(int64_t n);

@@ -259,11 +259,24 @@ __global__ void k_flatten(int64_t n, int32_t* __restrict__ parent) {
     parent[s] = uf_root(parent, (int)s);
 }
 
+// smallest original index per root; sorted slots of one group are mostly
+// adjacent, so lanes sharing a root combine before the atomic
 __global__ void k_min_index(int64_t n, const int32_t* __restrict__ parent,
                             const int32_t* __restrict__ perm, int32_t* __restrict__ minidx) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    atomicMin(minidx + parent[s], perm[s]);
+    const bool active = s < n;
+    const int32_t r = active ? parent[s] : -1;
+    const unsigned long long key = active ? (unsigned long long)(uint32_t)perm[s] : ~0ull;
+    uint64_t todo = __ballot(active);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lr = __shfl(r, leader, 64);
+        const bool mine = active && r == lr;
+        const uint64_t grp = __ballot(mine);
+        const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+        if ((int)(threadIdx.x & 63) == leader) atomicMin(minidx + lr, (int32_t)mn);
+        todo &= ~grp;
+    }
 }
 
 __global__ void k_write_labels(int64_t n, const int32_t* __restrict__ parent,
@@ -388,11 +401,13 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
 
     LinkArgs A{oct_start, oct_bits, cell_oct, hk, hv, mask, kout, sx, sy, sz, parent, n_oct, g};
     unsigned go = grid_for(n_oct, 256, 1ll << 31);
+    prof_begin("fof3d_link", st);
     if (g.autolink)
         k_link<true><<<go, 256, 0, st>>>(A);
     else
         k_link<false><<<go, 256, 0, st>>>(A);
     RS_HIP(hipGetLastError());
+    prof_end("fof3d_link", st, (double)n);
 
     k_flatten<<<gb, BT, 0, st>>>(n, parent);
     RS_TRY(fill_i32(minidx, 0x7fffffff, n, st));

@@ -29,11 +29,13 @@ namespace rs {
 // level 0
 // ---------------------------------------------------------------------------
 
-__global__ void k_p_count(const float* __restrict__ x, const float* __restrict__ y,
-                          const float* __restrict__ z, const float* __restrict__ vx,
-                          const float* __restrict__ vy, const float* __restrict__ vz,
-                          const int32_t* __restrict__ lab, int64_t n, float L,
-                          int32_t* __restrict__ cnt, int32_t* __restrict__ err) {
+// validation + sort keys: (label, index) pairs
+__global__ void k_p_keys(const float* __restrict__ x, const float* __restrict__ y,
+                         const float* __restrict__ z, const float* __restrict__ vx,
+                         const float* __restrict__ vy, const float* __restrict__ vz,
+                         const int32_t* __restrict__ lab, int64_t n, float L,
+                         uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                         int32_t* __restrict__ err) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     bool bad = !(x[i] >= 0.0f && x[i] < L) || !(y[i] >= 0.0f && y[i] < L) ||
@@ -44,85 +46,86 @@ __global__ void k_p_count(const float* __restrict__ x, const float* __restrict__
     int32_t l = lab[i];
     if (l < 0 || l >= n) {
         atomicOr(err, 2);
-        return;
+        l = 0;
     }
-    atomicAdd(cnt + l, 1);
+    keys[i] = (uint64_t)(uint32_t)l;
+    vals[i] = (int32_t)i;
 }
 
-__global__ void k_p_flag(int64_t n, const int32_t* __restrict__ cnt, int32_t min_group,
-                         int32_t* __restrict__ flag) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r < n) flag[r] = cnt[r] >= min_group ? 1 : 0;
+// run starts of equal labels in the sorted order
+__global__ void k_p_runflag(int64_t n, const uint64_t* __restrict__ slab,
+                            int32_t* __restrict__ flag) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) flag[p] = (p == 0 || slab[p] != slab[p - 1]) ? 1 : 0;
 }
 
-__global__ void k_p_gsize(int64_t n, const int32_t* __restrict__ cnt,
-                          const int32_t* __restrict__ flag, const int32_t* __restrict__ gid,
-                          int32_t* __restrict__ gsize, int32_t* __restrict__ gmin,
-                          int32_t* __restrict__ gfill) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n || !flag[r]) return;
-    int32_t g = gid[r];
-    gsize[g] = cnt[r];
-    gmin[g] = 0x7fffffff;
-    gfill[g] = 0;
+__global__ void k_p_runstart(int64_t n, const int32_t* __restrict__ flag,
+                             const int32_t* __restrict__ rex, int32_t* __restrict__ rstart) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n && flag[p]) rstart[rex[p]] = (int32_t)p;
 }
 
-__global__ void k_p_gmin(int64_t n, const int32_t* __restrict__ lab,
-                         const int32_t* __restrict__ flag, const int32_t* __restrict__ gid,
-                         int32_t* __restrict__ gmin, int32_t* __restrict__ deepest) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t l = lab[i];
-    if (flag[l]) {
-        int32_t g = gid[l];
-        atomicMin(gmin + g, (int32_t)i);
-        deepest[i] = g;
-    } else {
-        deepest[i] = -1;
-    }
+__global__ void k_p_keep(int32_t nruns, const int32_t* __restrict__ rstart, int32_t min_group,
+                         int32_t* __restrict__ keep, int32_t* __restrict__ klen) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    int32_t len = rstart[r + 1] - rstart[r];
+    bool k = len >= min_group;
+    keep[r] = k ? 1 : 0;
+    klen[r] = k ? len : 0;
 }
 
+// members packed per group in ascending particle index (the sort is stable)
 __global__ void k_p_fill(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
                          const float* __restrict__ z, const float* __restrict__ vx,
                          const float* __restrict__ vy, const float* __restrict__ vz,
-                         const int32_t* __restrict__ lab, const int32_t* __restrict__ flag,
-                         const int32_t* __restrict__ gid, const int32_t* __restrict__ goff,
-                         int32_t* __restrict__ gfill, Members A) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t l = lab[i];
-    if (!flag[l]) return;
-    int32_t g = gid[l];
-    int64_t p = (int64_t)goff[g] + atomicAdd(gfill + g, 1);
-    A.x[p] = x[i];
-    A.y[p] = y[i];
-    A.z[p] = z[i];
-    A.vx[p] = vx[i];
-    A.vy[p] = vy[i];
-    A.vz[p] = vz[i];
-    A.idx[p] = (int32_t)i;
+                         const int32_t* __restrict__ sidx, const int32_t* __restrict__ flag,
+                         const int32_t* __restrict__ rex, const int32_t* __restrict__ rstart,
+                         const int32_t* __restrict__ keep, const int32_t* __restrict__ gid,
+                         const int32_t* __restrict__ goff, Members A,
+                         int32_t* __restrict__ deepest) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t r = rex[p] + flag[p] - 1;
+    int32_t i = sidx[p];
+    if (!keep[r]) {
+        deepest[i] = -1;
+        return;
+    }
+    int64_t pos = (int64_t)goff[r] + (p - rstart[r]);
+    A.x[pos] = x[i];
+    A.y[pos] = y[i];
+    A.z[pos] = z[i];
+    A.vx[pos] = vx[i];
+    A.vy[pos] = vy[i];
+    A.vz[pos] = vz[i];
+    A.idx[pos] = i;
+    deepest[i] = gid[r];
 }
 
 // level-0 records; small groups into the bucket lists, large ones listed
-__global__ void k_p_class(int32_t G, const int32_t* __restrict__ gsize,
-                          const int32_t* __restrict__ gmin, const int32_t* __restrict__ goff,
+__global__ void k_p_class(int32_t nruns, const int32_t* __restrict__ rstart,
+                          const int32_t* __restrict__ keep, const int32_t* __restrict__ gid,
+                          const int32_t* __restrict__ goff, const int32_t* __restrict__ sidx,
                           NodeRec nr, SmallItem* __restrict__ buckets, int64_t stride,
                           int32_t* __restrict__ bcount, ChildOut* __restrict__ large,
                           int32_t* __restrict__ nlarge) {
-    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    int32_t sz = gsize[g];
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns || !keep[r]) return;
+    int32_t g = gid[r];
+    int32_t sz = rstart[r + 1] - rstart[r];
+    int32_t mi = sidx[rstart[r]];
     nr.level[g] = 0;
-    nr.minidx[g] = gmin[g];
+    nr.minidx[g] = mi;
     nr.parent[g] = -1;
     nr.size[g] = sz;
     if (sz <= SMALL_MAX) {
         int b = sz <= 64 ? 0 : sz <= 256 ? 1 : sz <= 1024 ? 2 : 3;   // small_bucket_of
         int p = atomicAdd(bcount + b, 1);
-        buckets[b * stride + p] = SmallItem{g, 0, sz, gmin[g], (int64_t)goff[g]};
+        buckets[b * stride + p] = SmallItem{g, 0, sz, mi, (int64_t)goff[r]};
     } else {
         int p = atomicAdd(nlarge, 1);
-        large[p] = ChildOut{g, sz, gmin[g], 0, (int64_t)goff[g]};
+        large[p] = ChildOut{g, sz, mi, 0, (int64_t)goff[r]};
     }
 }
 
@@ -184,10 +187,12 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
                          hipStream_t st) {
     const int BT = 256;
     *overflow = false;
-    // ---- arena 0: level-0 tables, records, output sort ----
+    // ---- arena 1: level-0 tables, records, output sort ----
     size_t bytes = 0;
     auto add = [&](size_t b) { bytes += arena_round(b); };
-    for (int k = 0; k < 8; k++) add(4 * (size_t)n);           // cnt flag gid gsize gmin goff gfill deepest
+    add(8 * (size_t)n); add(8 * (size_t)n);                   // label keys in / out
+    add(4 * (size_t)n); add(4 * (size_t)n);                   // index in / out
+    for (int k = 0; k < 8; k++) add(4 * ((size_t)n + 1));     // flag rex rstart keep klen gid goff deepest
     for (int k = 0; k < 7; k++) add(4 * (size_t)n);           // A
     for (int k = 0; k < 9; k++) add(4 * (size_t)cap);         // records
     add(8 * (size_t)cap); add(8 * (size_t)cap); add(4 * (size_t)cap); add(4 * (size_t)cap);
@@ -197,14 +202,18 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     add(sort_temp_bytes(cap > n ? cap : n)); add(scan_temp_bytes(n)); add(256);
     Arena* ar;
     RS_TRY(arena_reserve(1, bytes, &ar));
-    int32_t* cnt = take<int32_t>(ar, n);
-    int32_t* flag = take<int32_t>(ar, n);
-    int32_t* gid = take<int32_t>(ar, n);
-    int32_t* gsize = take<int32_t>(ar, n);
-    int32_t* gmin = take<int32_t>(ar, n);
-    int32_t* goff = take<int32_t>(ar, n);
-    int32_t* gfill = take<int32_t>(ar, n);
-    int32_t* deepest = take<int32_t>(ar, n);
+    uint64_t* lkin = take<uint64_t>(ar, n);
+    uint64_t* lkout = take<uint64_t>(ar, n);
+    int32_t* lvin = take<int32_t>(ar, n);
+    int32_t* sidx = take<int32_t>(ar, n);
+    int32_t* flag = take<int32_t>(ar, n + 1);
+    int32_t* rex = take<int32_t>(ar, n + 1);
+    int32_t* rstart = take<int32_t>(ar, n + 1);
+    int32_t* keep = take<int32_t>(ar, n + 1);
+    int32_t* klen = take<int32_t>(ar, n + 1);
+    int32_t* gid = take<int32_t>(ar, n + 1);
+    int32_t* goff = take<int32_t>(ar, n + 1);
+    int32_t* deepest = take<int32_t>(ar, n + 1);
     Members A;
     A.x = take<float>(ar, n); A.y = take<float>(ar, n); A.z = take<float>(ar, n);
     A.vx = take<float>(ar, n); A.vy = take<float>(ar, n); A.vz = take<float>(ar, n);
@@ -231,7 +240,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     size_t stb = sort_temp_bytes(cap > n ? cap : n);
     void* stemp = arena_take(ar, stb);
     void* ctemp = arena_take(ar, scan_temp_bytes(n));
-    int32_t* ctr = take<int32_t>(ar, 32);      // 0 err, 1 G, 2 M0, 3 count, 4 overflow, 8.. bcount, 12 nlarge
+    // counters: 0 err, 1 runs, 2 G, 3 node count, 4 overflow, 5 M0, 8..11 buckets, 12 nlarge
+    int32_t* ctr = take<int32_t>(ar, 32);
     if (!ctr) return RS_EINTERNAL;
     nr.count = ctr + 3;
     nr.overflow = ctr + 4;
@@ -240,27 +250,38 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
 
     unsigned gb = grid_for(n, BT, 1ll << 31);
     RS_HIP(hipMemsetAsync(ctr, 0, 32 * sizeof(int32_t), st));
-    RS_HIP(hipMemsetAsync(cnt, 0, 4 * (size_t)n, st));
-    k_p_count<<<gb, BT, 0, st>>>(x, y, z, vx, vy, vz, lab, n, L, cnt, ctr);
-    k_p_flag<<<gb, BT, 0, st>>>(n, cnt, min_group, flag);
+    k_p_keys<<<gb, BT, 0, st>>>(x, y, z, vx, vy, vz, lab, n, L, lkin, lvin, ctr);
     RS_HIP(hipGetLastError());
-    RS_TRY(scan_exclusive_i32(flag, gid, n, ctemp, ctr + 1, st));
+    int lbits = 1;
+    while (lbits < 31 && ((int64_t)1 << lbits) < n) lbits++;
+    RS_TRY(sort_pairs_u64_i32(lkin, lkout, lvin, sidx, n, lbits, stemp, stb, st));
+    k_p_runflag<<<gb, BT, 0, st>>>(n, lkout, flag);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(flag, rex, n, ctemp, ctr + 1, st));
+    k_p_runstart<<<gb, BT, 0, st>>>(n, flag, rex, rstart);
+    RS_HIP(hipGetLastError());
     RS_HIP(hipMemcpyAsync(hc, ctr, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
     if (hc[0] & 2) return RS_EINVAL;
     if (hc[0] & 1) return RS_ERANGE;
-    const int32_t G = hc[1];
+    const int32_t nruns = hc[1];
+    RS_TRY(fill_i32(rstart + nruns, (int32_t)n, 1, st));
+    k_p_keep<<<grid_for(nruns, BT, 1ll << 31), BT, 0, st>>>(nruns, rstart, min_group, keep, klen);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(keep, gid, nruns, ctemp, ctr + 2, st));
+    RS_TRY(scan_exclusive_i32(klen, goff, nruns, ctemp, ctr + 5, st));
+    RS_HIP(hipMemcpyAsync(hc, ctr, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    const int32_t G = hc[2];
     if (G > cap) {
         *overflow = true;
         return RS_OK;
     }
-    k_p_gsize<<<gb, BT, 0, st>>>(n, cnt, flag, gid, gsize, gmin, gfill);
-    k_p_gmin<<<gb, BT, 0, st>>>(n, lab, flag, gid, gmin, deepest);
-    RS_HIP(hipGetLastError());
-    RS_TRY(scan_exclusive_i32(gsize, goff, G, ctemp, ctr + 2, st));
-    k_p_fill<<<gb, BT, 0, st>>>(n, x, y, z, vx, vy, vz, lab, flag, gid, goff, gfill, A);
-    k_p_class<<<grid_for(G, BT, 1ll << 31), BT, 0, st>>>(G, gsize, gmin, goff, nr, buckets,
-                                                          bstride, ctr + 8, large0, ctr + 12);
+    k_p_fill<<<gb, BT, 0, st>>>(n, x, y, z, vx, vy, vz, sidx, flag, rex, rstart, keep, gid, goff,
+                                A, deepest);
+    k_p_class<<<grid_for(nruns, BT, 1ll << 31), BT, 0, st>>>(nruns, rstart, keep, gid, goff, sidx,
+                                                              nr, buckets, bstride, ctr + 8,
+                                                              large0, ctr + 12);
     RS_HIP(hipGetLastError());
     RS_TRY(fill_i32(nr.count, G, 1, st));
     RS_HIP(hipMemcpyAsync(hc, ctr, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));

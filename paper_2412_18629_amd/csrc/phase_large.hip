@@ -328,87 +328,100 @@ struct LKArgs {
     float slack;
 };
 
-template <bool WRAP>
-RS_DEV void tile_nn(const float* cx, const float* cy, const float* cz, const float* cu,
-                    const float* cv, const float* cw, int cnt, int self, float xi, float yi,
-                    float zi, float ui, float vi, float wi, float a, float c, float L, float h,
-                    float& best) {
-    for (int j = 0; j < cnt; j++) {
-        float d = phase_d2<WRAP>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j],
-                                 cw[j], a, c, L, h);
-        best = (j != self && d < best) ? d : best;
-    }
+RS_DEV float wave_min_f(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
-__global__ void __launch_bounds__(64) k_lnn(LKArgs A, float* __restrict__ d2out) {
-    __shared__ float cx[64], cy[64], cz[64], cu[64], cv[64], cw[64];
-    const int t = blockIdx.x, lane = threadIdx.x;
+// one query member, held uniformly by the whole wavefront
+struct Query {
+    float x, y, z, u, v, w;
+    float wq[3], uq[3];   // unwrapped position and velocity for box bounds
+};
+
+RS_DEV Query load_query(const Members& T, int64_t m, const LParam& P, const PhaseParams& pp) {
+    Query q;
+    q.x = T.x[m]; q.y = T.y[m]; q.z = T.z[m];
+    q.u = T.vx[m]; q.v = T.vy[m]; q.w = T.vz[m];
+    q.wq[0] = min_image(q.x - P.rx, pp.L, pp.h);
+    q.wq[1] = min_image(q.y - P.ry, pp.L, pp.h);
+    q.wq[2] = min_image(q.z - P.rz, pp.L, pp.h);
+    q.uq[0] = q.u; q.uq[1] = q.v; q.uq[2] = q.w;
+    return q;
+}
+
+RS_DEV float query_d2(const Members& T, int64_t m, const Query& q, const LParam& P,
+                      const PhaseParams& pp) {
+    float xj = T.x[m], yj = T.y[m], zj = T.z[m], uj = T.vx[m], vj = T.vy[m], wj = T.vz[m];
+    return P.nowrap
+        ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h)
+        : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h);
+}
+
+// Nearest-neighbour distance of every member.  One wavefront per tile of
+// queries, one query at a time: the 64 lanes bound 64 super-tile boxes (then
+// 64 tile boxes) against the query in parallel, and evaluate the 64 members
+// of each surviving tile, one pair per lane.  Boxes are re-checked against
+// the current best just before their members are read.
+__global__ void __launch_bounds__(256) k_lnn(LKArgs A, int ntiles, float* __restrict__ d2out) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntiles) return;
     const int v = A.tile_node[t];
     const LNode nd = A.nodes[v];
     const LParam P = A.prm[v];
     const Members& T = A.T;
     int64_t ts, te;
     tile_range(nd, t, &ts, &te);
-    const int64_t m = ts + lane;
-    const bool valid = m < te;
-    const int64_t mm = valid ? m : ts;
-    const float xi = T.x[mm], yi = T.y[mm], zi = T.z[mm];
-    const float ui = T.vx[mm], vi = T.vy[mm], wi = T.vz[mm];
-    const float w[3] = {min_image(xi - P.rx, A.pp.L, A.pp.h), min_image(yi - P.ry, A.pp.L, A.pp.h),
-                        min_image(zi - P.rz, A.pp.L, A.pp.h)};
-    const float u[3] = {ui, vi, wi};
-    float best = __builtin_huge_valf();
-
-    auto stage = [&](int64_t s0, int64_t s1) {
-        __syncthreads();
-        int64_t q = s0 + lane;
-        if (q < s1) {
-            cx[lane] = T.x[q]; cy[lane] = T.y[q]; cz[lane] = T.z[q];
-            cu[lane] = T.vx[q]; cv[lane] = T.vy[q]; cw[lane] = T.vz[q];
-        }
-        __syncthreads();
-        return (int)(s1 - s0);
-    };
-    auto scan = [&](int cnt, int self) {
-        if (P.nowrap)
-            tile_nn<false>(cx, cy, cz, cu, cv, cw, cnt, self, xi, yi, zi, ui, vi, wi, P.a, P.c,
-                           A.pp.L, A.pp.h, best);
-        else
-            tile_nn<true>(cx, cy, cz, cu, cv, cw, cnt, self, xi, yi, zi, ui, vi, wi, P.a, P.c,
-                          A.pp.L, A.pp.h, best);
-    };
-
-    scan(stage(ts, te), lane);
+    const int cnt = (int)(te - ts);
     const int sown = nd.super0 + (t - nd.tile0) / 64;
     const int send = nd.super0 + nd.nsuper;
-    int span = sown - nd.super0;
-    if (send - 1 - sown > span) span = send - 1 - sown;
-    for (int d = 0; d <= span; d++) {
-        for (int side = 0; side < 2; side++) {
-            if (d == 0 && side == 1) continue;
-            int s = side == 0 ? sown + d : sown - d;
-            if (s < nd.super0 || s >= send) continue;
-            if (P.cull) {
-                bool need = valid && box_lb(A.sbox + 12 * (int64_t)s, w, u, P.a, P.c, A.slack) < best;
-                if (!__any(need)) continue;
-            }
-            int u0 = nd.tile0 + 64 * (s - nd.super0);
-            int u1 = u0 + 64;
-            if (u1 > nd.tile0 + nd.ntile) u1 = nd.tile0 + nd.ntile;
-            for (int tu = u0; tu < u1; tu++) {
-                if (tu == t) continue;
-                if (P.cull) {
-                    bool need =
-                        valid && box_lb(A.tbox + 12 * (int64_t)tu, w, u, P.a, P.c, A.slack) < best;
-                    if (!__any(need)) continue;
-                }
+    const int tend = nd.tile0 + nd.ntile;
+    for (int qi = 0; qi < cnt; qi++) {
+        const int64_t qm = ts + qi;
+        const Query q = load_query(T, qm, P, A.pp);
+        float bl = __builtin_huge_valf();
+        if (lane < cnt && lane != qi) bl = query_d2(T, ts + lane, q, P, A.pp);
+        float best = wave_min_f(bl);
+        auto scan_super = [&](int s) {
+            const int u0 = nd.tile0 + 64 * (s - nd.super0);
+            const int u1 = u0 + 64 < tend ? u0 + 64 : tend;
+            const int u = u0 + lane;
+            bool need = u < u1 && u != t &&
+                        (!P.cull || box_lb(A.tbox + 12 * (int64_t)u, q.wq, q.uq, P.a, P.c,
+                                           A.slack) < best);
+            uint64_t mask = __ballot(need);
+            while (mask) {
+                const int uu = u0 + __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                if (P.cull &&
+                    !(box_lb(A.tbox + 12 * (int64_t)uu, q.wq, q.uq, P.a, P.c, A.slack) < best))
+                    continue;
                 int64_t q0, q1;
-                tile_range(nd, tu, &q0, &q1);
-                scan(stage(q0, q1), -1);
+                tile_range(nd, uu, &q0, &q1);
+                if (q0 + lane < q1) bl = fminf(bl, query_d2(T, q0 + lane, q, P, A.pp));
+                best = wave_min_f(bl);
+            }
+        };
+        scan_super(sown);
+        for (int sb = nd.super0; sb < send; sb += 64) {
+            const int s = sb + lane;
+            bool need = s < send && s != sown &&
+                        (!P.cull || box_lb(A.sbox + 12 * (int64_t)s, q.wq, q.uq, P.a, P.c,
+                                           A.slack) < best);
+            uint64_t mask = __ballot(need);
+            while (mask) {
+                const int ss = sb + __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                if (P.cull &&
+                    !(box_lb(A.sbox + 12 * (int64_t)ss, q.wq, q.uq, P.a, P.c, A.slack) < best))
+                    continue;
+                scan_super(ss);
             }
         }
+        if (lane == 0) d2out[qm] = best;
     }
-    if (valid) d2out[m] = best;
 }
 
 // ---------------------------------------------------------------------------
@@ -466,90 +479,63 @@ k_lpick(const int32_t* __restrict__ ghist, int shift, LParam* __restrict__ prm,
 // linking within l
 // ---------------------------------------------------------------------------
 
-template <bool WRAP>
-RS_DEV void tile_link(const float* cx, const float* cy, const float* cz, const float* cu,
-                      const float* cv, const float* cw, int cnt, int jmin, int64_t q0,
-                      bool act, int64_t m, float xi, float yi, float zi, float ui, float vi,
-                      float wi, float a, float c, float l2, float L, float h, int32_t* par) {
-    for (int j = jmin; j < cnt; j++) {
-        float d = phase_d2<WRAP>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j],
-                                 cw[j], a, c, L, h);
-        if (act && d <= l2) uf_unite(par, (int)m, (int)(q0 + j));
-    }
-}
-
-__global__ void __launch_bounds__(64)
-k_llink(LKArgs A, const float* __restrict__ d2, int32_t* __restrict__ par) {
-    __shared__ float cx[64], cy[64], cz[64], cu[64], cv[64], cw[64];
-    const int t = blockIdx.x, lane = threadIdx.x;
+// Links within l: one wavefront per tile of queries, one query at a time,
+// against later members only (own tile: later lanes; then later tiles of the
+// own super-tile; then later super-tiles), boxes bounded lane-parallel.
+// Queries without a neighbour within l cannot link and are skipped.
+__global__ void __launch_bounds__(256)
+k_llink(LKArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntiles) return;
     const int v = A.tile_node[t];
     const LNode nd = A.nodes[v];
     const LParam P = A.prm[v];
     const Members& T = A.T;
     int64_t ts, te;
     tile_range(nd, t, &ts, &te);
-    const int64_t m = ts + lane;
-    const bool valid = m < te;
-    const int64_t mm = valid ? m : ts;
-    const bool act = valid && d2[mm] <= P.l2;
-    if (!__any(act)) return;
-    const float xi = T.x[mm], yi = T.y[mm], zi = T.z[mm];
-    const float ui = T.vx[mm], vi = T.vy[mm], wi = T.vz[mm];
-    const float w[3] = {min_image(xi - P.rx, A.pp.L, A.pp.h), min_image(yi - P.ry, A.pp.L, A.pp.h),
-                        min_image(zi - P.rz, A.pp.L, A.pp.h)};
-    const float u[3] = {ui, vi, wi};
-
-    auto stage = [&](int64_t s0, int64_t s1) {
-        __syncthreads();
-        int64_t q = s0 + lane;
-        if (q < s1) {
-            cx[lane] = T.x[q]; cy[lane] = T.y[q]; cz[lane] = T.z[q];
-            cu[lane] = T.vx[q]; cv[lane] = T.vy[q]; cw[lane] = T.vz[q];
-        }
-        __syncthreads();
-        return (int)(s1 - s0);
-    };
-    auto run = [&](int cnt, int jmin, int64_t q0) {
-        if (P.nowrap)
-            tile_link<false>(cx, cy, cz, cu, cv, cw, cnt, jmin, q0, act, m, xi, yi, zi, ui, vi,
-                             wi, P.a, P.c, P.l2, A.pp.L, A.pp.h, par);
-        else
-            tile_link<true>(cx, cy, cz, cu, cv, cw, cnt, jmin, q0, act, m, xi, yi, zi, ui, vi, wi,
-                            P.a, P.c, P.l2, A.pp.L, A.pp.h, par);
-    };
-
-    // own tile: pairs (lane, j) with j > lane
-    {
-        int cnt = stage(ts, te);
-        for (int j = 0; j < cnt; j++) {
-            float d = P.nowrap
-                ? phase_d2<false>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j], cw[j],
-                                  P.a, P.c, A.pp.L, A.pp.h)
-                : phase_d2<true>(xi, yi, zi, ui, vi, wi, cx[j], cy[j], cz[j], cu[j], cv[j], cw[j],
-                                 P.a, P.c, A.pp.L, A.pp.h);
-            if (act && j > lane && d <= P.l2) uf_unite(par, (int)m, (int)(ts + j));
-        }
-    }
+    const int cnt = (int)(te - ts);
     const int sown = nd.super0 + (t - nd.tile0) / 64;
     const int send = nd.super0 + nd.nsuper;
-    for (int s = sown; s < send; s++) {
-        if (P.cull) {
-            bool need = act && !(box_lb(A.sbox + 12 * (int64_t)s, w, u, P.a, P.c, A.slack) > P.l2);
-            if (!__any(need)) continue;
+    const int tend = nd.tile0 + nd.ntile;
+    const float l2 = P.l2;
+    for (int qi = 0; qi < cnt; qi++) {
+        const int64_t qm = ts + qi;
+        if (!(d2[qm] <= l2)) continue;
+        const Query q = load_query(T, qm, P, A.pp);
+        if (lane > qi && lane < cnt) {
+            if (query_d2(T, ts + lane, q, P, A.pp) <= l2) uf_unite(par, (int)qm, (int)(ts + lane));
         }
-        int u0 = nd.tile0 + 64 * (s - nd.super0);
-        int u1 = u0 + 64;
-        if (u1 > nd.tile0 + nd.ntile) u1 = nd.tile0 + nd.ntile;
-        if (u0 <= t) u0 = t + 1;
-        for (int tu = u0; tu < u1; tu++) {
-            if (P.cull) {
-                bool need =
-                    act && !(box_lb(A.tbox + 12 * (int64_t)tu, w, u, P.a, P.c, A.slack) > P.l2);
-                if (!__any(need)) continue;
+        auto scan_super = [&](int s, int ufrom) {
+            int u0 = nd.tile0 + 64 * (s - nd.super0);
+            const int u1 = u0 + 64 < tend ? u0 + 64 : tend;
+            if (ufrom > u0) u0 = ufrom;
+            const int u = u0 + lane;
+            bool need = u < u1 &&
+                        (!P.cull || !(box_lb(A.tbox + 12 * (int64_t)u, q.wq, q.uq, P.a, P.c,
+                                             A.slack) > l2));
+            uint64_t mask = __ballot(need);
+            while (mask) {
+                const int uu = u0 + __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                int64_t q0, q1;
+                tile_range(nd, uu, &q0, &q1);
+                const int64_t m = q0 + lane;
+                if (m < q1 && query_d2(T, m, q, P, A.pp) <= l2) uf_unite(par, (int)qm, (int)m);
             }
-            int64_t q0, q1;
-            tile_range(nd, tu, &q0, &q1);
-            run(stage(q0, q1), 0, q0);
+        };
+        scan_super(sown, t + 1);
+        for (int sb = sown + 1; sb < send; sb += 64) {
+            const int s = sb + lane;
+            bool need = s < send &&
+                        (!P.cull || !(box_lb(A.sbox + 12 * (int64_t)s, q.wq, q.uq, P.a, P.c,
+                                             A.slack) > l2));
+            uint64_t mask = __ballot(need);
+            while (mask) {
+                const int ss = sb + __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                scan_super(ss, 0);
+            }
         }
     }
 }
@@ -572,14 +558,29 @@ __global__ void k_lflat(int64_t m, int32_t* __restrict__ par, int32_t* __restric
     mpk[t] = ~0ull;
 }
 
+// component sizes and packed (index, slot) minima, aggregated per wavefront
+// over runs of members sharing a root
 __global__ void k_lstat(int64_t m, const int32_t* __restrict__ par,
                         const int32_t* __restrict__ idx, int32_t* __restrict__ cnt,
                         unsigned long long* __restrict__ mpk) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= m) return;
-    int32_t r = par[t];
-    atomicAdd(cnt + r, 1);
-    atomicMin(mpk + r, ((unsigned long long)(uint32_t)idx[t] << 32) | (uint32_t)t);
+    const bool active = t < m;
+    const int32_t r = active ? par[t] : -1;
+    const unsigned long long key =
+        active ? (((unsigned long long)(uint32_t)idx[t] << 32) | (uint32_t)t) : ~0ull;
+    uint64_t todo = __ballot(active);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lr = __shfl(r, leader, 64);
+        const bool mine = active && r == lr;
+        const uint64_t grp = __ballot(mine);
+        const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+        if ((int)(threadIdx.x & 63) == leader) {
+            atomicAdd(cnt + lr, __popcll(grp));
+            atomicMin(mpk + lr, mn);
+        }
+        todo &= ~grp;
+    }
 }
 
 struct LCounters {
@@ -634,11 +635,24 @@ __global__ void k_lscatter(int64_t m, const int32_t* __restrict__ par, Members T
                            int32_t* __restrict__ cfill, const int8_t* __restrict__ cclass,
                            Members S, Members N, int32_t* __restrict__ deepest) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= m) return;
-    int32_t r = par[t];
-    int32_t s = cslot[r];
-    if (s < 0) return;
-    int64_t pos = coff[r] + atomicAdd(cfill + r, 1);
+    const int32_t r = t < m ? par[t] : -1;
+    const int32_t s = r >= 0 ? cslot[r] : -1;
+    const bool active = s >= 0;
+    // slots within the child: one atomic per run of lanes with the same root
+    int64_t pos = 0;
+    uint64_t todo = __ballot(active);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lr = __shfl(r, leader, 64);
+        const bool mine = active && r == lr;
+        const uint64_t grp = __ballot(mine);
+        int base = 0;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(cfill + lr, __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (mine) pos = coff[r] + base + __popcll(grp & lanemask_lt());
+        todo &= ~grp;
+    }
+    if (!active) return;
     Members D = cclass[r] ? N : S;
     D.x[pos] = T.x[t];
     D.y[pos] = T.y[t];
@@ -821,7 +835,9 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     RS_HIP(hipGetLastError());
     LKArgs A{w->tile_node, w->nodes, w->prm, w->tbox, w->sbox, w->T, pp,
              8.0f * pp.L * 5.9604645e-08f};
-    k_lnn<<<tiles, 64, 0, st>>>(A, w->d2);
+    prof_begin("phase_large_nn", st);
+    k_lnn<<<(tiles + 3) / 4, 256, 0, st>>>(A, tiles, w->d2);
+    prof_end("phase_large_nn", st, (double)M);
     RS_HIP(hipGetLastError());
     for (int pass = 0; pass < 4; pass++) {
         int shift = 24 - 8 * pass;
@@ -831,7 +847,9 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
         RS_HIP(hipGetLastError());
     }
     k_liota<<<gm, BT, 0, st>>>(M, w->par);
-    k_llink<<<tiles, 64, 0, st>>>(A, w->d2, w->par);
+    prof_begin("phase_large_link", st);
+    k_llink<<<(tiles + 3) / 4, 256, 0, st>>>(A, tiles, w->d2, w->par);
+    prof_end("phase_large_link", st, (double)M);
     k_lflat<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk);
     k_lstat<<<gm, BT, 0, st>>>(M, w->par, w->T.idx, w->cnt, w->mpk);
     RS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(LCounters), st));

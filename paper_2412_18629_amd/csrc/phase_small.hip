@@ -388,8 +388,10 @@ static int launch_small(const SmallItem* items, int n_items, const Members& mb,
     RS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     unsigned grid = (unsigned)(n_items < (1 << 20) ? n_items : (1 << 20));
+    prof_begin("phase_small", st);
     kern<<<grid, NT, lds, st>>>(items, n_items, mb, nr, pp, deepest);
     RS_HIP(hipGetLastError());
+    prof_end("phase_small", st, 0.0);
     return RS_OK;
 }
 

@@ -4,6 +4,11 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 namespace rs {
 
 // ---------------------------------------------------------------------------
@@ -63,6 +68,61 @@ int host_scratch(void** out, size_t bytes) {
     }
     *out = g_host_scratch[dev];
     return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing (HIP events on the launching stream)
+// ---------------------------------------------------------------------------
+
+struct ProfRec {
+    std::vector<hipEvent_t> start, stop;
+    std::vector<double> units;
+    double done_ms = 0.0, done_units = 0.0;
+    int64_t done_launches = 0;
+};
+
+static bool g_prof_on = false;
+static std::map<std::string, ProfRec> g_prof;
+static std::map<std::string, hipEvent_t> g_prof_open;
+static std::mutex g_prof_mu;
+
+void prof_begin(const char* name, hipStream_t st) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    g_prof_open[name] = e;
+}
+
+void prof_end(const char* name, hipStream_t st, double units) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    auto it = g_prof_open.find(name);
+    if (it == g_prof_open.end()) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    ProfRec& r = g_prof[name];
+    r.start.push_back(it->second);
+    r.stop.push_back(e);
+    r.units.push_back(units);
+    g_prof_open.erase(it);
+}
+
+static void prof_drain(ProfRec& r) {
+    for (size_t i = 0; i < r.start.size(); i++) {
+        float ms = 0.0f;
+        (void)hipEventSynchronize(r.stop[i]);
+        if (hipEventElapsedTime(&ms, r.start[i], r.stop[i]) == hipSuccess) r.done_ms += ms;
+        r.done_units += r.units[i];
+        r.done_launches += 1;
+        (void)hipEventDestroy(r.start[i]);
+        (void)hipEventDestroy(r.stop[i]);
+    }
+    r.start.clear();
+    r.stop.clear();
+    r.units.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -208,3 +268,34 @@ int sort_pairs_u64_i32(const uint64_t* kin, uint64_t* kout, const int32_t* vin,
 }
 
 }  // namespace rs
+
+extern "C" {
+
+int rs_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(rs::g_prof_mu);
+    if (!on) {
+        for (auto& kv : rs::g_prof) rs::prof_drain(kv.second);
+        rs::g_prof.clear();
+    }
+    rs::g_prof_on = on != 0;
+    return RS_OK;
+}
+
+int rs_profile_get(const char* name, double* total_ms, int64_t* launches, double* units) {
+    if (!name || !total_ms || !launches || !units) return RS_EINVAL;
+    std::lock_guard<std::mutex> g(rs::g_prof_mu);
+    auto it = rs::g_prof.find(name);
+    if (it == rs::g_prof.end()) {
+        *total_ms = 0.0;
+        *launches = 0;
+        *units = 0.0;
+        return RS_OK;
+    }
+    rs::prof_drain(it->second);
+    *total_ms = it->second.done_ms;
+    *launches = it->second.done_launches;
+    *units = it->second.done_units;
+    return RS_OK;
+}
+
+}  // extern "C"
