@@ -53,10 +53,61 @@ struct ChildOut {
     int64_t off;                         // first member in its member buffer
 };
 
-struct LNode;
-struct LItem;
-struct LParam;
-struct LCounters;
+struct LNode {              // one large node of the current level
+    int32_t slot, size, minidx, level;
+    int64_t in_off;         // first member in the input buffer
+    int64_t t_off;          // first member in tile order
+    int32_t tile0, ntile, super0, nsuper;
+};
+
+struct LItem {              // (node, chunk) work item
+    int32_t v, len;
+    int64_t in_start, t_start;
+};
+
+struct LParam {
+    float a, c, sa, sc;
+    float rx, ry, rz;       // reference member position
+    float cx, cy, cz;       // mean position (for the sort key only)
+    float cu, cv, cw;       // mean velocity (sort key only)
+    int32_t nowrap, cull;
+    uint32_t pf, pm;        // radix-select prefix and mask
+    int32_t kk;             // remaining rank
+    float l2;
+};
+
+struct LCounters {
+    int32_t n_small, n_large;
+    unsigned long long tot_small, tot_large;
+};
+
+// search tree over the members of the large nodes of one level
+struct TreeBuf {
+    int32_t *istart, *iend, *ientry, *cfirst, *ccount;   // internal nodes [cap_inode]
+    int32_t *estart, *eend, *enode;                       // child entries [cap_entry]
+    float* erec;   // [16 * cap_entry]: lo xyz uvw, hi xyz uvw, then (int) start end cfirst ccount
+    int32_t* leaf_of;                                     // [members] leaf entry of each member
+    int32_t *n_inode, *n_entry, *overflow;                // device counters
+    int32_t cap_inode, cap_entry;
+};
+
+struct TArgs {
+    const int32_t* tile_node;
+    const LNode* nodes;
+    const LParam* prm;
+    const int32_t* root;     // [node] root internal node
+    TreeBuf tb;
+    Members T;
+    PhaseParams pp;
+    float slack;
+};
+
+int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
+               const Members& T, const int32_t* mnode, const LParam* prm,
+               const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st);
+int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st);
+int tree_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st);
+
 
 // device buffers of the large-node pipeline, sized by the level-0 total of
 // large-node members (which bounds every later level)
@@ -84,6 +135,8 @@ struct LargeWork {
     ChildOut* large_out;
     void* sort_temp;
     size_t sort_temp_bytes;
+    TreeBuf tb;
+    int32_t* root;
 };
 
 size_t large_work_bytes(int64_t m);

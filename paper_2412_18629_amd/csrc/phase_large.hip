@@ -25,28 +25,8 @@
 
 namespace rs {
 
-struct LNode {              // one large node of the current level
-    int32_t slot, size, minidx, level;
-    int64_t in_off;         // first member in the input buffer
-    int64_t t_off;          // first member in tile order
-    int32_t tile0, ntile, super0, nsuper;
-};
 
-struct LItem {              // (node, chunk) work item
-    int32_t v, len;
-    int64_t in_start, t_start;
-};
 
-struct LParam {
-    float a, c, sa, sc;
-    float rx, ry, rz;       // reference member position
-    float cx, cy, cz;       // mean position (for the sort key only)
-    float cu, cv, cw;       // mean velocity (sort key only)
-    int32_t nowrap, cull;
-    uint32_t pf, pm;        // radix-select prefix and mask
-    int32_t kk;             // remaining rank
-    float l2;
-};
 
 // ---------------------------------------------------------------------------
 
@@ -328,102 +308,6 @@ struct LKArgs {
     float slack;
 };
 
-RS_DEV float wave_min_f(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// one query member, held uniformly by the whole wavefront
-struct Query {
-    float x, y, z, u, v, w;
-    float wq[3], uq[3];   // unwrapped position and velocity for box bounds
-};
-
-RS_DEV Query load_query(const Members& T, int64_t m, const LParam& P, const PhaseParams& pp) {
-    Query q;
-    q.x = T.x[m]; q.y = T.y[m]; q.z = T.z[m];
-    q.u = T.vx[m]; q.v = T.vy[m]; q.w = T.vz[m];
-    q.wq[0] = min_image(q.x - P.rx, pp.L, pp.h);
-    q.wq[1] = min_image(q.y - P.ry, pp.L, pp.h);
-    q.wq[2] = min_image(q.z - P.rz, pp.L, pp.h);
-    q.uq[0] = q.u; q.uq[1] = q.v; q.uq[2] = q.w;
-    return q;
-}
-
-RS_DEV float query_d2(const Members& T, int64_t m, const Query& q, const LParam& P,
-                      const PhaseParams& pp) {
-    float xj = T.x[m], yj = T.y[m], zj = T.z[m], uj = T.vx[m], vj = T.vy[m], wj = T.vz[m];
-    return P.nowrap
-        ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h)
-        : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h);
-}
-
-// Nearest-neighbour distance of every member.  One wavefront per tile of
-// queries, one query at a time: the 64 lanes bound 64 super-tile boxes (then
-// 64 tile boxes) against the query in parallel, and evaluate the 64 members
-// of each surviving tile, one pair per lane.  Boxes are re-checked against
-// the current best just before their members are read.
-__global__ void __launch_bounds__(256) k_lnn(LKArgs A, int ntiles, float* __restrict__ d2out) {
-    const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= ntiles) return;
-    const int v = A.tile_node[t];
-    const LNode nd = A.nodes[v];
-    const LParam P = A.prm[v];
-    const Members& T = A.T;
-    int64_t ts, te;
-    tile_range(nd, t, &ts, &te);
-    const int cnt = (int)(te - ts);
-    const int sown = nd.super0 + (t - nd.tile0) / 64;
-    const int send = nd.super0 + nd.nsuper;
-    const int tend = nd.tile0 + nd.ntile;
-    for (int qi = 0; qi < cnt; qi++) {
-        const int64_t qm = ts + qi;
-        const Query q = load_query(T, qm, P, A.pp);
-        float bl = __builtin_huge_valf();
-        if (lane < cnt && lane != qi) bl = query_d2(T, ts + lane, q, P, A.pp);
-        float best = wave_min_f(bl);
-        auto scan_super = [&](int s) {
-            const int u0 = nd.tile0 + 64 * (s - nd.super0);
-            const int u1 = u0 + 64 < tend ? u0 + 64 : tend;
-            const int u = u0 + lane;
-            bool need = u < u1 && u != t &&
-                        (!P.cull || box_lb(A.tbox + 12 * (int64_t)u, q.wq, q.uq, P.a, P.c,
-                                           A.slack) < best);
-            uint64_t mask = __ballot(need);
-            while (mask) {
-                const int uu = u0 + __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                if (P.cull &&
-                    !(box_lb(A.tbox + 12 * (int64_t)uu, q.wq, q.uq, P.a, P.c, A.slack) < best))
-                    continue;
-                int64_t q0, q1;
-                tile_range(nd, uu, &q0, &q1);
-                if (q0 + lane < q1) bl = fminf(bl, query_d2(T, q0 + lane, q, P, A.pp));
-                best = wave_min_f(bl);
-            }
-        };
-        scan_super(sown);
-        for (int sb = nd.super0; sb < send; sb += 64) {
-            const int s = sb + lane;
-            bool need = s < send && s != sown &&
-                        (!P.cull || box_lb(A.sbox + 12 * (int64_t)s, q.wq, q.uq, P.a, P.c,
-                                           A.slack) < best);
-            uint64_t mask = __ballot(need);
-            while (mask) {
-                const int ss = sb + __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                if (P.cull &&
-                    !(box_lb(A.sbox + 12 * (int64_t)ss, q.wq, q.uq, P.a, P.c, A.slack) < best))
-                    continue;
-                scan_super(ss);
-            }
-        }
-        if (lane == 0) d2out[qm] = best;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // per-node radix select over the d^2 bit patterns
 // ---------------------------------------------------------------------------
@@ -479,67 +363,6 @@ k_lpick(const int32_t* __restrict__ ghist, int shift, LParam* __restrict__ prm,
 // linking within l
 // ---------------------------------------------------------------------------
 
-// Links within l: one wavefront per tile of queries, one query at a time,
-// against later members only (own tile: later lanes; then later tiles of the
-// own super-tile; then later super-tiles), boxes bounded lane-parallel.
-// Queries without a neighbour within l cannot link and are skipped.
-__global__ void __launch_bounds__(256)
-k_llink(LKArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
-    const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= ntiles) return;
-    const int v = A.tile_node[t];
-    const LNode nd = A.nodes[v];
-    const LParam P = A.prm[v];
-    const Members& T = A.T;
-    int64_t ts, te;
-    tile_range(nd, t, &ts, &te);
-    const int cnt = (int)(te - ts);
-    const int sown = nd.super0 + (t - nd.tile0) / 64;
-    const int send = nd.super0 + nd.nsuper;
-    const int tend = nd.tile0 + nd.ntile;
-    const float l2 = P.l2;
-    for (int qi = 0; qi < cnt; qi++) {
-        const int64_t qm = ts + qi;
-        if (!(d2[qm] <= l2)) continue;
-        const Query q = load_query(T, qm, P, A.pp);
-        if (lane > qi && lane < cnt) {
-            if (query_d2(T, ts + lane, q, P, A.pp) <= l2) uf_unite(par, (int)qm, (int)(ts + lane));
-        }
-        auto scan_super = [&](int s, int ufrom) {
-            int u0 = nd.tile0 + 64 * (s - nd.super0);
-            const int u1 = u0 + 64 < tend ? u0 + 64 : tend;
-            if (ufrom > u0) u0 = ufrom;
-            const int u = u0 + lane;
-            bool need = u < u1 &&
-                        (!P.cull || !(box_lb(A.tbox + 12 * (int64_t)u, q.wq, q.uq, P.a, P.c,
-                                             A.slack) > l2));
-            uint64_t mask = __ballot(need);
-            while (mask) {
-                const int uu = u0 + __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                int64_t q0, q1;
-                tile_range(nd, uu, &q0, &q1);
-                const int64_t m = q0 + lane;
-                if (m < q1 && query_d2(T, m, q, P, A.pp) <= l2) uf_unite(par, (int)qm, (int)m);
-            }
-        };
-        scan_super(sown, t + 1);
-        for (int sb = sown + 1; sb < send; sb += 64) {
-            const int s = sb + lane;
-            bool need = s < send &&
-                        (!P.cull || !(box_lb(A.sbox + 12 * (int64_t)s, q.wq, q.uq, P.a, P.c,
-                                             A.slack) > l2));
-            uint64_t mask = __ballot(need);
-            while (mask) {
-                const int ss = sb + __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                scan_super(ss, 0);
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // components and children
 // ---------------------------------------------------------------------------
@@ -583,10 +406,6 @@ __global__ void k_lstat(int64_t m, const int32_t* __restrict__ par,
     }
 }
 
-struct LCounters {
-    int32_t n_small, n_large;
-    unsigned long long tot_small, tot_large;
-};
 
 __global__ void k_lchild(int64_t m, const int32_t* __restrict__ par,
                          const int32_t* __restrict__ cnt,
@@ -701,6 +520,10 @@ size_t large_work_bytes(int64_t m) {
     add(sizeof(LCounters)); add(sizeof(SmallItem) * small); add(sizeof(SmallItem) * 4 * small);
     add(64); add(sizeof(ChildOut) * nodes);
     add(sort_temp_bytes(m));
+    int64_t cap_inode = m / 8 + nodes + 64, cap_entry = m + m / 8 + nodes + 64;
+    for (int k = 0; k < 5; k++) add(4 * cap_inode);            // tree internal nodes
+    for (int k = 0; k < 3; k++) add(4 * cap_entry);            // tree entries
+    add(4 * 16 * cap_entry); add(4 * m); add(64); add(4 * nodes);
     return b + 4096;
 }
 
@@ -747,7 +570,27 @@ int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
     w->large_out = take<ChildOut>(ar, w->cap_nodes);
     w->sort_temp_bytes = sort_temp_bytes(m);
     w->sort_temp = arena_take(ar, w->sort_temp_bytes);
-    return w->sort_temp ? RS_OK : RS_EINTERNAL;
+    const int64_t cap_inode = m / 8 + w->cap_nodes + 64;
+    const int64_t cap_entry = m + m / 8 + w->cap_nodes + 64;
+    TreeBuf& tb = w->tb;
+    tb.istart = take<int32_t>(ar, cap_inode);
+    tb.iend = take<int32_t>(ar, cap_inode);
+    tb.ientry = take<int32_t>(ar, cap_inode);
+    tb.cfirst = take<int32_t>(ar, cap_inode);
+    tb.ccount = take<int32_t>(ar, cap_inode);
+    tb.estart = take<int32_t>(ar, cap_entry);
+    tb.eend = take<int32_t>(ar, cap_entry);
+    tb.enode = take<int32_t>(ar, cap_entry);
+    tb.erec = take<float>(ar, 16 * cap_entry);
+    tb.leaf_of = take<int32_t>(ar, m);
+    int32_t* ctr = take<int32_t>(ar, 16);
+    tb.n_inode = ctr;
+    tb.n_entry = ctr + 1;
+    tb.overflow = ctr + 2;
+    tb.cap_inode = (int32_t)cap_inode;
+    tb.cap_entry = (int32_t)cap_entry;
+    w->root = take<int32_t>(ar, w->cap_nodes);
+    return (w->sort_temp && w->root) ? RS_OK : RS_EINTERNAL;
 }
 
 // Launches the small-subtree kernels over a device list of small items whose
@@ -833,12 +676,14 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     k_lsbox<<<supers, 64, 0, st>>>(w->super_node, w->nodes, w->tbox, w->sbox);
     k_lcull<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->sbox, pp, w->prm);
     RS_HIP(hipGetLastError());
-    LKArgs A{w->tile_node, w->nodes, w->prm, w->tbox, w->sbox, w->T, pp,
+    std::vector<int32_t> tree_levels;
+    RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
+                      &tree_levels, st));
+    TArgs TA{w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
              8.0f * pp.L * 5.9604645e-08f};
     prof_begin("phase_large_nn", st);
-    k_lnn<<<(tiles + 3) / 4, 256, 0, st>>>(A, tiles, w->d2);
+    RS_TRY(tree_nn(TA, tiles, w->d2, st));
     prof_end("phase_large_nn", st, (double)M);
-    RS_HIP(hipGetLastError());
     for (int pass = 0; pass < 4; pass++) {
         int shift = 24 - 8 * pass;
         RS_HIP(hipMemsetAsync(w->ghist, 0, 4 * 256 * (size_t)nv, st));
@@ -848,7 +693,7 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     }
     k_liota<<<gm, BT, 0, st>>>(M, w->par);
     prof_begin("phase_large_link", st);
-    k_llink<<<(tiles + 3) / 4, 256, 0, st>>>(A, tiles, w->d2, w->par);
+    RS_TRY(tree_link(TA, tiles, w->d2, w->par, st));
     prof_end("phase_large_link", st, (double)M);
     k_lflat<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk);
     k_lstat<<<gm, BT, 0, st>>>(M, w->par, w->T.idx, w->cnt, w->mpk);

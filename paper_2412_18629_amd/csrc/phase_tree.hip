@@ -1,0 +1,535 @@
+// phase_tree.hip -- 6D search tree over the Morton-sorted members of the
+// large nodes of one level, and the nearest-neighbour / linking traversals.
+//
+// Tree: an internal node is a Morton-prefix cell (6 key bits per level, one
+// per dimension) with more than 64 members.  Its children are the non-empty
+// sub-cells of the next level: sub-cells with more than 64 members become
+// internal nodes, runs of consecutive smaller sub-cells are packed into
+// leaves of at most 64 members.  Cells of the finest level are cut into
+// 64-member leaves.  Every child entry carries the exact bounding box of its
+// members (positions unwrapped around the node's reference member, raw
+// velocities), so boxes are tight at every level.
+//
+// Traversal: one wavefront handles one query at a time.  The 64 lanes bound
+// 64 child boxes in parallel; surviving leaves are scanned one candidate per
+// lane, surviving internal children go onto a per-wavefront LDS stack.
+#include "phase_common.h"
+
+namespace rs {
+
+
+
+constexpr uint64_t MORTON_MASK = (1ull << 42) - 1ull;
+constexpr int TREE_LEVELS = 7;       // 42 Morton bits, 6 per level
+constexpr int STACK_PER_WAVE = 520;  // >= 64 internal children x 8 levels
+
+// first position in [lo, hi) whose Morton bits are >= target
+RS_DEV int32_t morton_lower_bound(const uint64_t* __restrict__ keys, int32_t lo, int32_t hi,
+                                  uint64_t target) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if ((keys[mid] & MORTON_MASK) < target) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One wavefront (one block) per internal node of `level`: find its children
+// by lane-parallel binary search (lane d -> digit d), pack the small ones into
+// leaves, allocate entries and child internal nodes.
+__global__ void __launch_bounds__(64)
+k_tree_split(const uint64_t* __restrict__ keys, int32_t node_begin, int level, TreeBuf tb) {
+    const int lane = threadIdx.x;
+    const int32_t x = node_begin + blockIdx.x;
+    const int32_t start = tb.istart[x], end = tb.iend[x];
+    const int32_t cnt_all = end - start;
+    if (level >= TREE_LEVELS) {
+        // finest cell: cut into 64-member leaves
+        const int32_t nch = (cnt_all + 63) / 64;
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(tb.n_entry, nch);
+        base = __shfl(base, 0, 64);
+        const bool ok = base + nch <= tb.cap_entry;
+        for (int32_t k = lane; k < nch && ok; k += 64) {
+            int32_t e = base + k;
+            tb.estart[e] = start + 64 * k;
+            tb.eend[e] = min(start + 64 * (k + 1), end);
+            tb.enode[e] = -1;
+        }
+        if (lane == 0) {
+            if (!ok) atomicOr(tb.overflow, 1);
+            tb.cfirst[x] = ok ? base : 0;
+            tb.ccount[x] = ok ? nch : 0;
+        }
+        return;
+    }
+    const int shift = 42 - 6 * (level + 1);
+    const uint64_t prefix = (keys[start] & MORTON_MASK) >> (shift + 6);
+    const uint64_t target = ((prefix << 6) | (uint64_t)lane) << shift;
+    const int32_t lo = morton_lower_bound(keys, start, end, target);
+    int32_t hi = __shfl_down(lo, 1, 64);
+    if (lane == 63) hi = end;
+    const int32_t cnt = hi - lo;
+    // every lane runs the packing walk over the 64 digits (values broadcast
+    // by shuffles), so all counts agree; lane 0 writes
+    int32_t n_int = 0, n_ent = 0, run = 0;
+    for (int d = 0; d < 64; d++) {
+        const int32_t c = __shfl(cnt, d, 64);
+        if (c == 0) continue;
+        if (c > 64) {
+            if (run) { n_ent++; run = 0; }
+            n_int++;
+            n_ent++;
+        } else if (run + c > 64) {
+            n_ent++;
+            run = c;
+        } else {
+            run += c;
+        }
+    }
+    if (run) n_ent++;
+    int32_t ebase = 0, ibase = 0;
+    if (lane == 0) {
+        ebase = atomicAdd(tb.n_entry, n_ent);
+        ibase = atomicAdd(tb.n_inode, n_int);
+    }
+    ebase = __shfl(ebase, 0, 64);
+    ibase = __shfl(ibase, 0, 64);
+    const bool ok = ebase + n_ent <= tb.cap_entry && ibase + n_int <= tb.cap_inode;
+    if (lane == 0) {
+        if (!ok) atomicOr(tb.overflow, 1);
+        tb.cfirst[x] = ok ? ebase : 0;
+        tb.ccount[x] = ok ? n_ent : 0;
+    }
+    if (!ok) return;
+    int32_t e = ebase, in = ibase, rs0 = -1, re0 = -1;
+    run = 0;
+    for (int d = 0; d < 64; d++) {
+        const int32_t c = __shfl(cnt, d, 64);
+        const int32_t l0 = __shfl(lo, d, 64);
+        if (c == 0) continue;
+        if (c > 64) {
+            if (run) {
+                if (lane == 0) { tb.estart[e] = rs0; tb.eend[e] = re0; tb.enode[e] = -1; }
+                e++;
+                run = 0;
+            }
+            if (lane == 0) {
+                tb.estart[e] = l0; tb.eend[e] = l0 + c; tb.enode[e] = in;
+                tb.istart[in] = l0; tb.iend[in] = l0 + c; tb.ientry[in] = e;
+            }
+            in++;
+            e++;
+        } else if (run + c > 64) {
+            if (lane == 0) { tb.estart[e] = rs0; tb.eend[e] = re0; tb.enode[e] = -1; }
+            e++;
+            rs0 = l0; re0 = l0 + c; run = c;
+        } else {
+            if (!run) rs0 = l0;
+            re0 = l0 + c;
+            run += c;
+        }
+    }
+    if (run && lane == 0) { tb.estart[e] = rs0; tb.eend[e] = re0; tb.enode[e] = -1; }
+}
+
+RS_DEV float wmin(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+RS_DEV float wmax(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// leaf boxes (wave per entry) and the leaf of every member
+__global__ void __launch_bounds__(256)
+k_tree_leafbox(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict__ mnode,
+               const LParam* __restrict__ prm, PhaseParams pp) {
+    const int lane = threadIdx.x & 63;
+    const int32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= n_entry || tb.enode[e] >= 0) return;
+    const int32_t s = tb.estart[e], t = tb.eend[e];
+    const int32_t m = s + lane;
+    const bool ok = m < t;
+    float c[6] = {0, 0, 0, 0, 0, 0};
+    if (ok) {
+        const LParam P = prm[mnode[m]];
+        c[0] = min_image(T.x[m] - P.rx, pp.L, pp.h);
+        c[1] = min_image(T.y[m] - P.ry, pp.L, pp.h);
+        c[2] = min_image(T.z[m] - P.rz, pp.L, pp.h);
+        c[3] = T.vx[m];
+        c[4] = T.vy[m];
+        c[5] = T.vz[m];
+        tb.leaf_of[m] = e;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        float lo = wmin(ok ? c[d] : __builtin_huge_valf());
+        float hi = wmax(ok ? c[d] : -__builtin_huge_valf());
+        if (lane == 0) {
+            tb.erec[16 * (int64_t)e + d] = lo;
+            tb.erec[16 * (int64_t)e + 6 + d] = hi;
+        }
+    }
+    if (lane == 0) {
+        int32_t* ri = reinterpret_cast<int32_t*>(tb.erec + 16 * (int64_t)e);
+        ri[12] = s;
+        ri[13] = t;
+        ri[14] = -1;
+        ri[15] = 0;
+    }
+}
+
+// internal-node boxes of one level (children done before parents)
+__global__ void __launch_bounds__(256)
+k_tree_nodebox(int32_t node_begin, int32_t node_end, TreeBuf tb) {
+    const int lane = threadIdx.x & 63;
+    const int32_t x = node_begin + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= node_end) return;
+    const int32_t f = tb.cfirst[x], n = tb.ccount[x];
+    float lo[6], hi[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        lo[d] = __builtin_huge_valf();
+        hi[d] = -__builtin_huge_valf();
+    }
+    for (int32_t k = lane; k < n; k += 64) {
+        const float* b = tb.erec + 16 * (int64_t)(f + k);
+#pragma unroll
+        for (int d = 0; d < 6; d++) {
+            lo[d] = fminf(lo[d], b[d]);
+            hi[d] = fmaxf(hi[d], b[6 + d]);
+        }
+    }
+    const int32_t pe = tb.ientry[x];
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        float l = wmin(lo[d]), h = wmax(hi[d]);
+        if (lane == 0 && pe >= 0) {
+            tb.erec[16 * (int64_t)pe + d] = l;
+            tb.erec[16 * (int64_t)pe + 6 + d] = h;
+        }
+    }
+    if (lane == 0 && pe >= 0) {
+        int32_t* ri = reinterpret_cast<int32_t*>(tb.erec + 16 * (int64_t)pe);
+        ri[12] = tb.istart[x];
+        ri[13] = tb.iend[x];
+        ri[14] = f;
+        ri[15] = n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// traversals
+// ---------------------------------------------------------------------------
+
+struct TQuery {
+    float x, y, z, u, v, w;
+    float wq[3], uq[3];
+};
+
+RS_DEV TQuery tq_load(const Members& T, int64_t m, const LParam& P, const PhaseParams& pp) {
+    TQuery q;
+    q.x = T.x[m]; q.y = T.y[m]; q.z = T.z[m];
+    q.u = T.vx[m]; q.v = T.vy[m]; q.w = T.vz[m];
+    q.wq[0] = min_image(q.x - P.rx, pp.L, pp.h);
+    q.wq[1] = min_image(q.y - P.ry, pp.L, pp.h);
+    q.wq[2] = min_image(q.z - P.rz, pp.L, pp.h);
+    q.uq[0] = q.u; q.uq[1] = q.v; q.uq[2] = q.w;
+    return q;
+}
+
+RS_DEV float tq_d2(const Members& T, int64_t m, const TQuery& q, const LParam& P,
+                   const PhaseParams& pp) {
+    float xj = T.x[m], yj = T.y[m], zj = T.z[m], uj = T.vx[m], vj = T.vy[m], wj = T.vz[m];
+    return P.nowrap
+        ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h)
+        : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h);
+}
+
+// one child-entry record, read with four 16-byte loads
+struct Rec {
+    float lo[6], hi[6];
+    int32_t start, end, cfirst, ccount;   // cfirst < 0: leaf
+};
+
+RS_DEV Rec rec_load(const float* __restrict__ erec, int32_t k) {
+    const float4* p = reinterpret_cast<const float4*>(erec + 16 * (int64_t)k);
+    float4 a = p[0], b = p[1], c = p[2], d = p[3];
+    Rec r;
+    r.lo[0] = a.x; r.lo[1] = a.y; r.lo[2] = a.z; r.lo[3] = a.w; r.lo[4] = b.x; r.lo[5] = b.y;
+    r.hi[0] = b.z; r.hi[1] = b.w; r.hi[2] = c.x; r.hi[3] = c.y; r.hi[4] = c.z; r.hi[5] = c.w;
+    r.start = __float_as_int(d.x);
+    r.end = __float_as_int(d.y);
+    r.cfirst = __float_as_int(d.z);
+    r.ccount = __float_as_int(d.w);
+    return r;
+}
+
+// exact lower bound of the computed d^2 from the query to any member of a
+// record's box (slack: absolute on unwrapped positions, covering
+// the rounding of x - x_ref, of the pair difference and of the image shift;
+// relative on velocities and on the bound itself)
+RS_DEV float rec_lb(const Rec& r, const TQuery& q, float a, float c, float slack) {
+    float sp = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        float g = fmaxf(fmaxf(r.lo[d] - q.wq[d], q.wq[d] - r.hi[d]), 0.0f);
+        g = fmaxf(g - slack, 0.0f);
+        sp += g * g;
+        float h = fmaxf(fmaxf(r.lo[3 + d] - q.uq[d], q.uq[d] - r.hi[3 + d]), 0.0f) * 0.99999905f;
+        sv += h * h;
+    }
+    return (a * sp + c * sv) * 0.99999f;
+}
+
+struct StackEnt {
+    int32_t cfirst, ccount;
+    float lb;
+};
+
+// nearest-neighbour d^2 of every member (exact): own leaf first, then a
+// depth-first descent from the node's root.  One wavefront per tile of
+// queries, one query at a time; child records are bounded lane-parallel,
+// surviving leaves are scanned four at a time with independent loads.
+__global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __restrict__ d2out) {
+    __shared__ StackEnt stk[STACK_PER_WAVE];
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int v = A.tile_node[t];
+    const LNode nd = A.nodes[v];
+    const LParam P = A.prm[v];
+    const Members& T = A.T;
+    const TreeBuf& tb = A.tb;
+    const int64_t ts = nd.t_off + 64ll * (t - nd.tile0);
+    const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
+    const bool cull = P.cull != 0;
+    const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
+    for (int64_t qm = ts; qm < te; qm++) {
+        const TQuery q = tq_load(T, qm, P, A.pp);
+        const int32_t e0 = tb.leaf_of[qm];
+        const int32_t* r0 = reinterpret_cast<const int32_t*>(tb.erec + 16 * (int64_t)e0);
+        float bl = __builtin_huge_valf();
+        {
+            const int64_t m = r0[12] + lane;
+            if (m < r0[13] && m != qm) bl = tq_d2(T, m, q, P, A.pp);
+        }
+        float best = wmin(bl);
+        if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
+        int sp = 1;
+        __syncthreads();
+        while (sp > 0) {
+            sp--;
+            const StackEnt se = stk[sp];
+            __syncthreads();
+            if (cull && !(se.lb < best)) continue;
+            for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
+                const int32_t k = se.cfirst + b0 + lane;
+                Rec r;
+                bool need = false;
+                float lb = 0.0f;
+                if (b0 + lane < se.ccount && k != e0) {
+                    r = rec_load(tb.erec, k);
+                    lb = cull ? rec_lb(r, q, P.a, P.c, A.slack) : 0.0f;
+                    need = lb < best;
+                } else {
+                    r.start = r.end = 0;
+                    r.cfirst = -1;
+                    r.ccount = 0;
+                }
+                const bool leaf = r.cfirst < 0;
+                const uint64_t imask = __ballot(need && !leaf);
+                if (need && !leaf)
+                    stk[sp + __popcll(imask & lanemask_lt())] = StackEnt{r.cfirst, r.ccount, lb};
+                sp += __popcll(imask);
+                __syncthreads();
+                uint64_t mk = __ballot(need && leaf);
+                while (mk) {
+                    // up to four leaves: member loads issued together
+                    int32_t s4[4], e4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (mk) {
+                            const int src = __ffsll((unsigned long long)mk) - 1;
+                            mk &= mk - 1;
+                            s4[j] = __shfl(r.start, src, 64);
+                            e4[j] = __shfl(r.end, src, 64);
+                        } else {
+                            s4[j] = e4[j] = 0;
+                        }
+                    }
+                    float d4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int64_t m = s4[j] + lane;
+                        d4[j] = m < e4[j] ? tq_d2(T, m, q, P, A.pp) : __builtin_huge_valf();
+                    }
+                    bl = fminf(bl, fminf(fminf(d4[0], d4[1]), fminf(d4[2], d4[3])));
+                    best = wmin(bl);
+                }
+            }
+        }
+        if (lane == 0) d2out[qm] = best;
+    }
+}
+
+// links within l against later members (member index > query): own leaf,
+// then a descent that prunes boxes farther than l and subtrees that hold no
+// later member; leaves scanned four at a time
+__global__ void __launch_bounds__(64)
+k_tree_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
+    __shared__ StackEnt stk[STACK_PER_WAVE];
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int v = A.tile_node[t];
+    const LNode nd = A.nodes[v];
+    const LParam P = A.prm[v];
+    const Members& T = A.T;
+    const TreeBuf& tb = A.tb;
+    const int64_t ts = nd.t_off + 64ll * (t - nd.tile0);
+    const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
+    const bool cull = P.cull != 0;
+    const float l2 = P.l2;
+    const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
+    for (int64_t qm = ts; qm < te; qm++) {
+        if (!(d2[qm] <= l2)) continue;
+        const TQuery q = tq_load(T, qm, P, A.pp);
+        const int32_t e0 = tb.leaf_of[qm];
+        const int32_t* r0 = reinterpret_cast<const int32_t*>(tb.erec + 16 * (int64_t)e0);
+        {
+            const int64_t m = r0[12] + lane;
+            if (m < r0[13] && m > qm && tq_d2(T, m, q, P, A.pp) <= l2)
+                uf_unite(par, (int)qm, (int)m);
+        }
+        if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
+        int sp = 1;
+        __syncthreads();
+        while (sp > 0) {
+            sp--;
+            const StackEnt se = stk[sp];
+            __syncthreads();
+            for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
+                const int32_t k = se.cfirst + b0 + lane;
+                Rec r;
+                bool need = false;
+                if (b0 + lane < se.ccount && k != e0) {
+                    r = rec_load(tb.erec, k);
+                    need = r.end > qm + 1 &&
+                           (!cull || !(rec_lb(r, q, P.a, P.c, A.slack) > l2));
+                } else {
+                    r.start = r.end = 0;
+                    r.cfirst = -1;
+                    r.ccount = 0;
+                }
+                const bool leaf = r.cfirst < 0;
+                const uint64_t imask = __ballot(need && !leaf);
+                if (need && !leaf)
+                    stk[sp + __popcll(imask & lanemask_lt())] = StackEnt{r.cfirst, r.ccount, 0.0f};
+                sp += __popcll(imask);
+                __syncthreads();
+                uint64_t mk = __ballot(need && leaf);
+                while (mk) {
+                    int32_t s4[4], e4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (mk) {
+                            const int src = __ffsll((unsigned long long)mk) - 1;
+                            mk &= mk - 1;
+                            s4[j] = __shfl(r.start, src, 64);
+                            e4[j] = __shfl(r.end, src, 64);
+                        } else {
+                            s4[j] = e4[j] = 0;
+                        }
+                    }
+                    bool hit[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int64_t m = s4[j] + lane;
+                        hit[j] = m < e4[j] && m > qm && tq_d2(T, m, q, P, A.pp) <= l2;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (hit[j]) uf_unite(par, (int)qm, (int)(s4[j] + lane));
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host: build the tree of one level and run the traversals
+// ---------------------------------------------------------------------------
+
+__global__ void k_tree_roots(int nv, const LNode* __restrict__ nodes, TreeBuf tb,
+                             int32_t* __restrict__ root) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    tb.istart[v] = (int32_t)nodes[v].t_off;
+    tb.iend[v] = (int32_t)(nodes[v].t_off + nodes[v].size);
+    tb.ientry[v] = -1;
+    root[v] = v;
+}
+
+int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
+               const Members& T, const int32_t* mnode, const LParam* prm,
+               const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st) {
+    int32_t* hc = nullptr;
+    RS_TRY(host_scratch((void**)&hc, 64));
+    RS_HIP(hipMemsetAsync(tb.n_entry, 0, sizeof(int32_t), st));
+    RS_HIP(hipMemsetAsync(tb.overflow, 0, sizeof(int32_t), st));
+    RS_TRY(fill_i32(tb.n_inode, nv, 1, st));
+    k_tree_roots<<<grid_for(nv, 64), 64, 0, st>>>(nv, nodes, tb, root);
+    RS_HIP(hipGetLastError());
+    level_begin->clear();
+    int32_t b = 0, e = nv;
+    for (int level = 0; level <= TREE_LEVELS; level++) {
+        level_begin->push_back(b);
+        if (e > b) {
+            k_tree_split<<<e - b, 64, 0, st>>>(skeys, b, level, tb);
+            RS_HIP(hipGetLastError());
+        }
+        RS_HIP(hipMemcpyAsync(hc, tb.n_inode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RS_HIP(hipMemcpyAsync(hc + 1, tb.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+        if (hc[1]) return RS_EINTERNAL;
+        b = e;
+        e = hc[0];
+        if (e == b) break;
+    }
+    level_begin->push_back(b);
+    RS_HIP(hipMemcpyAsync(hc, tb.n_entry, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    const int32_t n_entry = hc[0];
+    if (n_entry > 0) {
+        k_tree_leafbox<<<(n_entry + 3) / 4, 256, 0, st>>>(n_entry, tb, T, mnode, prm, pp);
+        RS_HIP(hipGetLastError());
+    }
+    // internal boxes, deepest level first
+    for (int l = (int)level_begin->size() - 2; l >= 0; l--) {
+        int32_t lb = (*level_begin)[l], le = (*level_begin)[l + 1];
+        if (le > lb) {
+            k_tree_nodebox<<<(le - lb + 3) / 4, 256, 0, st>>>(lb, le, tb);
+            RS_HIP(hipGetLastError());
+        }
+    }
+    return RS_OK;
+}
+
+int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st) {
+    k_tree_nn<<<ntiles, 64, 0, st>>>(A, ntiles, d2);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+int tree_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
+    k_tree_link<<<ntiles, 64, 0, st>>>(A, ntiles, d2, par);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+}  // namespace rs
