@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--config", default="c512")
     ap.add_argument("--form", default="batched", choices=["batched", "plain"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized device buffer 3 times (a plain "
+                         "copy kernel of known size, for calibrating byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's hot path runs on a single MI355X; "
@@ -136,6 +139,13 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(arrs, cfg)
+    if args.probe_copy > 0:
+        src = torch.ones(args.probe_copy * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["probe_copy_bytes"] = src.numel() * 4
     print(json.dumps(line), flush=True)
     return 0
 
