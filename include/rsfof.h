@@ -49,9 +49,19 @@ typedef enum {
 enum {
     RS_PLAIN = 0,    /* one level-0 group per launch sequence, host-driven */
     RS_BATCHED = 1,  /* all groups and levels through size-bucketed kernels */
-    RS_LEARNED = 2   /* batched, linking length proposed by the MLP and verified
+    RS_LEARNED = 2,  /* batched, linking length proposed by the MLP and verified
                         by exact counting in a bracket (implies RS_BATCHED) */
+    RS_FEATURES = 0x100  /* OR-able: also return the per-node proposer features */
 };
+
+/* Proposer features per node (float): [0] ln N; [1..3] per-axis share of the
+ * position dispersion; [4..6] per-axis share of the velocity dispersion;
+ * [7..14] fractions of members with |x - mean| / sigma_x in the bins with
+ * edges {0.25, 0.5, 0.75, 1, 1.5, 2, 3}; [15..22] the same for
+ * |v - mean| / sigma_v; [23] recursion level. */
+#define RS_NFEAT 24
+/* MLP parameters: W1[64][24], b1[64], W2[64][64], b2[64], W3[64], b3 */
+#define RS_MLP_NPARAM 5825
 
 /*
  * rs_fof3d -- 3D friends-of-friends over one periodic box (paper,
@@ -98,6 +108,7 @@ typedef struct rs_tree {
     int64_t n_accepted;  /* RS_LEARNED: nodes whose proposed bracket held */
     int64_t n_fallback;  /* RS_LEARNED: nodes that fell back to the full search */
     int64_t n_levels;    /* number of levels (max level + 1), 0 if no nodes */
+    float* features;     /* [n_nodes * RS_NFEAT] with RS_FEATURES, else NULL */
 } rs_tree;
 
 /*
@@ -118,8 +129,11 @@ typedef struct rs_tree {
  *   min_group   >= 2, smallest 3D group that is split (paper configs: 10).
  *   min_sub     >= 2, smallest child kept (10).
  *   f           0 < f <= 1, linked fraction (0.7).
- *   flags       RS_PLAIN, RS_BATCHED or RS_LEARNED.
- *   model       (host) weights blob from rs_model_pack for RS_LEARNED, else NULL.
+ *   flags       RS_PLAIN, RS_BATCHED or RS_LEARNED, optionally | RS_FEATURES.
+ *   model       (host) proposer blob ("RSM1" + floats, see below) for
+ *               RS_LEARNED, else NULL.  RS_LEARNED applies the proposal to
+ *               nodes above the workgroup size (2048 members); smaller nodes
+ *               are split exactly as in RS_BATCHED.
  *   out         (host) receives a new rs_tree* (release with rs_free).
  * Returns after synchronising `stream`.
  */
@@ -131,9 +145,36 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z,
                        void* stream);
 
 /*
+ * Linking-length proposer (SURVEY-level "learned part"; it never decides a
+ * result: RS_LEARNED verifies every proposal exactly and falls back to the
+ * full nearest-neighbour search).  All pointers are device pointers.
+ *
+ * rs_mlp_forward:   y[n] = MLP(params, X[n][RS_NFEAT]) in fp32 (X standardised).
+ * rs_mlp_grad:      grad[RS_MLP_NPARAM] and loss = mean((y - t)^2) over n samples.
+ * rs_mlp_train_step: one Adam step (lr, beta 0.9/0.999, eps 1e-8; `step` >= 1
+ *                   is the 1-based step count) on params with moments m, v;
+ *                   writes the minibatch loss before the update to *loss.
+ * rs_mlp_standardize: X <- (X - mean) / std per feature; with compute != 0
+ *                   mean and std are first computed from X (std 1 if ~0).
+ * rs_mlp_infer:     out[n] = MLP(model, features) with bf16 weights and
+ *                   activations and fp32 accumulation; model = mean[24],
+ *                   std[24], params[RS_MLP_NPARAM]; features unstandardised.
+ * rs_phase_fof_batch's `model` (host) is that same float layout preceded by
+ * the 4-byte tag "RSM1".  Each returns RS_OK or RS_EINVAL / RS_EDEVICE.
+ */
+int rs_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream);
+int rs_mlp_grad(const float* params, const float* X, const float* t, int64_t n, float* grad,
+                float* loss, void* stream);
+int rs_mlp_train_step(float* params, float* m, float* v, int64_t step, const float* X,
+                      const float* t, int64_t n, float lr, float* loss, void* stream);
+int rs_mlp_standardize(float* X, int64_t n, float* mean, float* stdv, int compute, void* stream);
+int rs_mlp_infer(const float* model, int64_t n, const float* features, float* out, void* stream);
+
+/*
  * Instrumentation (not part of the method).  While enabled, the library
  * records HIP events on the launching stream around its main kernels
- * ("fof3d_link", "phase_small", "phase_large_nn", "phase_large_link") and
+ * ("fof3d_link", "phase_small", "phase_large_nn", "phase_large_link",
+ * "phase_large_nn_fallback") and
  * accumulates their elapsed time, launch count and processed work units
  * (particles or node members).  rs_profile_enable(0) clears the records.
  * rs_profile_get synchronises on the recorded events; unknown names report

@@ -17,9 +17,13 @@ LIB_PATH = os.path.join(_HERE, "librsfof.so")
 RS_OK, RS_EINVAL, RS_ERANGE, RS_ENOMEM, RS_EDEVICE, RS_EINTERNAL, RS_ENOTIMPL = (
     0, -1, -2, -3, -4, -5, -6)
 RS_PLAIN, RS_BATCHED, RS_LEARNED = 0, 1, 2
+RS_FEATURES = 0x100
+RS_NFEAT = 24
+RS_MLP_NPARAM = 5825
 
 EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
-            "rs_profile_enable", "rs_profile_get")
+            "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
+            "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer")
 
 
 class RsError(RuntimeError):
@@ -35,7 +39,8 @@ class _Tree(ctypes.Structure):
                 ("l2", ctypes.c_void_p), ("a", ctypes.c_void_p), ("c", ctypes.c_void_p),
                 ("sx2", ctypes.c_void_p), ("sv2", ctypes.c_void_p),
                 ("deepest", ctypes.c_void_p), ("n_accepted", ctypes.c_int64),
-                ("n_fallback", ctypes.c_int64), ("n_levels", ctypes.c_int64)]
+                ("n_fallback", ctypes.c_int64), ("n_levels", ctypes.c_int64),
+                ("features", ctypes.c_void_p)]
 
 
 _lib = None
@@ -67,6 +72,14 @@ def load():
     lib.rs_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64),
                                    ctypes.POINTER(f64)]
     lib.rs_profile_get.restype = ctypes.c_int
+    lib.rs_mlp_forward.argtypes = [P, P, i64, P, P]
+    lib.rs_mlp_grad.argtypes = [P, P, P, i64, P, P, P]
+    lib.rs_mlp_train_step.argtypes = [P, P, P, i64, P, P, i64, f32, P, P]
+    lib.rs_mlp_standardize.argtypes = [P, i64, P, P, ctypes.c_int, P]
+    lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
+    for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
+               "rs_mlp_infer"):
+        getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -167,6 +180,9 @@ def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_s
         res["n_accepted"] = int(t.n_accepted)
         res["n_fallback"] = int(t.n_fallback)
         res["n_levels"] = int(t.n_levels)
+        if t.features:
+            res["features"] = _copy_out(t.features, m * RS_NFEAT, torch.float32,
+                                        x.device).view(m, RS_NFEAT)
         torch.cuda.current_stream().synchronize()
     finally:
         lib.rs_free(out)
@@ -185,3 +201,72 @@ def rs_profile_get(name: str):
     if rc != RS_OK:
         raise RsError(rc, "rs_profile_get")
     return ms.value, int(n.value), u.value
+
+
+# ---------------------------------------------------------------------------
+# linking-length proposer (MLP) entry points
+# ---------------------------------------------------------------------------
+
+def _ck(rc, where):
+    if rc != RS_OK:
+        raise RsError(rc, where)
+
+
+def rs_mlp_forward(params, X, stream=None):
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _ck(load().rs_mlp_forward(_dev(params, torch.float32, "params"), _dev(X, torch.float32, "X"),
+                              X.shape[0], _dev(y, torch.float32, "y"), _stream(stream)),
+        "rs_mlp_forward")
+    return y
+
+
+def rs_mlp_grad(params, X, t, stream=None):
+    g = torch.empty(RS_MLP_NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _ck(load().rs_mlp_grad(_dev(params, torch.float32, "params"), _dev(X, torch.float32, "X"),
+                           _dev(t, torch.float32, "t"), X.shape[0], _dev(g, torch.float32, "g"),
+                           _dev(loss, torch.float32, "loss"), _stream(stream)), "rs_mlp_grad")
+    return g, loss
+
+
+def rs_mlp_train_step(params, m, v, step, X, t, lr, loss, stream=None):
+    _ck(load().rs_mlp_train_step(_dev(params, torch.float32, "params"),
+                                 _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"),
+                                 int(step), _dev(X, torch.float32, "X"),
+                                 _dev(t, torch.float32, "t"), X.shape[0], float(lr),
+                                 _dev(loss, torch.float32, "loss"), _stream(stream)),
+        "rs_mlp_train_step")
+
+
+def rs_mlp_standardize(X, mean, std, compute=True, stream=None):
+    _ck(load().rs_mlp_standardize(_dev(X, torch.float32, "X"), X.shape[0],
+                                  _dev(mean, torch.float32, "mean"),
+                                  _dev(std, torch.float32, "std"), 1 if compute else 0,
+                                  _stream(stream)), "rs_mlp_standardize")
+
+
+def rs_mlp_infer(model, feats, stream=None):
+    out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+    _ck(load().rs_mlp_infer(_dev(model, torch.float32, "model"),
+                            feats.shape[0], _dev(feats, torch.float32, "features"),
+                            _dev(out, torch.float32, "out"), _stream(stream)), "rs_mlp_infer")
+    return out
+
+
+def pack_model(mean, std, params) -> bytes:
+    """The proposer blob rs_phase_fof_batch takes: b"RSM1" + float32
+    mean[24], std[24], params[5825]."""
+    import numpy as np
+    body = np.concatenate([np.asarray(mean, np.float32).ravel(), np.asarray(std, np.float32).ravel(),
+                           np.asarray(params, np.float32).ravel()])
+    if body.size != 2 * RS_NFEAT + RS_MLP_NPARAM:
+        raise ValueError("model has the wrong size")
+    return b"RSM1" + body.astype("<f4").tobytes()
+
+
+def unpack_model(blob: bytes):
+    import numpy as np
+    if blob[:4] != b"RSM1":
+        raise ValueError("not a proposer blob")
+    body = np.frombuffer(blob[4:], dtype="<f4")
+    return body[:RS_NFEAT], body[RS_NFEAT:2 * RS_NFEAT], body[2 * RS_NFEAT:]

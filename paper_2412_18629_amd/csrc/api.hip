@@ -51,8 +51,8 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
     if (!(box > 0.0f) || !isfinite(box)) return RS_EINVAL;
     if (min_group < 2 || min_sub < 2) return RS_EINVAL;
     if (!(f > 0.0 && f <= 1.0)) return RS_EINVAL;
-    if (flags > RS_LEARNED) return RS_EINVAL;
-    if (flags == RS_LEARNED && !model) return RS_EINVAL;
+    if ((flags & ~(uint32_t)RS_FEATURES) > RS_LEARNED) return RS_EINVAL;
+    if ((flags & 0xffu) == RS_LEARNED && !model) return RS_EINVAL;
     if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !fof_labels)) return RS_EINVAL;
     RS_TRY(rs::device_ready());
     return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,

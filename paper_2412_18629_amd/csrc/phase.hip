@@ -17,6 +17,7 @@
 // run the same kernels and give identical results.
 #include <math.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -164,6 +165,14 @@ __global__ void k_o_nodes(int32_t m, const int32_t* __restrict__ order,
     t.sv2[r] = nr.sv2[s];
 }
 
+__global__ void k_o_feat(int32_t m, const int32_t* __restrict__ order,
+                         const float* __restrict__ feat, float* __restrict__ out) {
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= (int64_t)m * RS_NFEAT) return;
+    int32_t r = (int32_t)(q / RS_NFEAT), i = (int32_t)(q % RS_NFEAT);
+    out[q] = feat[(int64_t)order[r] * RS_NFEAT + i];
+}
+
 __global__ void k_o_deep(int64_t n, const int32_t* __restrict__ deepest,
                          const int32_t* __restrict__ canon, int32_t* __restrict__ out) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -183,8 +192,8 @@ void tree_release(rs_tree* t) {
 static int phase_attempt(const float* x, const float* y, const float* z, const float* vx,
                          const float* vy, const float* vz, int64_t n, float L,
                          const int32_t* lab, int32_t min_group, const PhaseParams& pp,
-                         uint32_t flags, int64_t cap, rs_tree** out, bool* overflow,
-                         hipStream_t st) {
+                         uint32_t form, const float* model_host, int64_t cap, rs_tree** out,
+                         bool* overflow, hipStream_t st) {
     const int BT = 256;
     *overflow = false;
     // ---- arena 1: level-0 tables, records, output sort ----
@@ -200,6 +209,10 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     add(sizeof(SmallItem) * 4 * (size_t)(n / 2 + 2));          // level-0 buckets
     add(sizeof(ChildOut) * (size_t)(n / (SMALL_MAX + 1) + 2));
     add(sort_temp_bytes(cap > n ? cap : n)); add(scan_temp_bytes(n)); add(256);
+    const bool want_feat = pp.want_feat != 0;
+    if (want_feat) add(4 * (size_t)cap * RS_NFEAT);
+    const size_t model_floats = 2 * RS_NFEAT + RS_MLP_NPARAM;
+    add(4 * model_floats);
     Arena* ar;
     RS_TRY(arena_reserve(1, bytes, &ar));
     uint64_t* lkin = take<uint64_t>(ar, n);
@@ -229,6 +242,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     nr.sx2 = take<float>(ar, cap);
     nr.sv2 = take<float>(ar, cap);
     nr.cap = (int32_t)cap;
+    nr.feat = want_feat ? take<float>(ar, (size_t)cap * RS_NFEAT) : nullptr;
+    float* model_dev = take<float>(ar, model_floats);
     uint64_t* okin = take<uint64_t>(ar, cap);
     uint64_t* okout = take<uint64_t>(ar, cap);
     int32_t* ovin = take<int32_t>(ar, cap);
@@ -301,13 +316,19 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
 
     // ---- large-node work space (arena 2) ----
     LargeWork lw;
+    int64_t n_acc = 0, n_fb = 0;
     if (nlarge > 0) {
         Arena* ar2;
         RS_TRY(arena_reserve(2, large_work_bytes(mlarge), &ar2));
         RS_TRY(large_work_carve(ar2, mlarge, &lw));
+        if (form == RS_LEARNED) {
+            RS_HIP(hipMemcpyAsync(model_dev, model_host, 4 * model_floats, hipMemcpyHostToDevice,
+                                  st));
+            lw.model = model_dev;
+        }
     }
 
-    if (flags == RS_PLAIN) {
+    if (form == RS_PLAIN) {
         // one level-0 group per launch sequence, in slot order
         std::vector<SmallItem> hs;
         for (int b = 0; b < 4; b++) {
@@ -335,7 +356,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
                 std::vector<ChildOut> cur{large[li]}, nxt;
                 const Members* in = &A;
                 while (!cur.empty()) {
-                    RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, st));
+                    RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc,
+                                       &n_fb, st));
                     cur.swap(nxt);
                     in = &lw.N;
                 }
@@ -348,7 +370,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         std::vector<ChildOut> cur = large, nxt;
         const Members* in = &A;
         while (!cur.empty()) {
-            RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, st));
+            RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc, &n_fb,
+                               st));
             cur.swap(nxt);
             in = &lw.N;
         }
@@ -371,7 +394,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         RS_HIP(hipGetLastError());
     }
     size_t nodes_bytes = arena_round(4 * (size_t)(m > 0 ? m : 1));
-    size_t total = 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1));
+    size_t feat_bytes = want_feat ? arena_round(4 * (size_t)(m > 0 ? m : 1) * RS_NFEAT) : 0;
+    size_t total = 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)) + feat_bytes;
     rs_tree* t = (rs_tree*)calloc(1, sizeof(rs_tree));
     if (!t) return RS_ENOMEM;
     char* blk = nullptr;
@@ -393,7 +417,15 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     t->sx2 = (float*)(blk + 7 * nodes_bytes);
     t->sv2 = (float*)(blk + 8 * nodes_bytes);
     t->deepest = (int32_t*)(blk + 9 * nodes_bytes);
+    t->features = want_feat
+        ? (float*)(blk + 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)))
+        : nullptr;
+    t->n_accepted = n_acc;
+    t->n_fallback = n_fb;
     int rc = RS_OK;
+    if (want_feat && m > 0)
+        k_o_feat<<<grid_for((int64_t)m * RS_NFEAT, BT, 1ll << 31), BT, 0, st>>>(m, order, nr.feat,
+                                                                             t->features);
     if (m > 0) k_o_nodes<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, canon, nr, *t);
     if (n > 0) k_o_deep<<<gb, BT, 0, st>>>(n, deepest, canon, t->deepest);
     if (hipGetLastError() != hipSuccess) rc = RS_EDEVICE;
@@ -417,9 +449,14 @@ int phase_run(const float* x, const float* y, const float* z, const float* vx,
               const float* vy, const float* vz, int64_t n, float L, const int32_t* labels,
               int32_t min_group, int32_t min_sub, double f, uint32_t flags, const void* model,
               rs_tree** out, hipStream_t st) {
-    (void)model;
-    if (flags == RS_LEARNED) return RS_ENOTIMPL;
+    const uint32_t form = flags & 0xffu;
+    const float* model_host = nullptr;
+    if (form == RS_LEARNED) {
+        if (!model || memcmp(model, "RSM1", 4) != 0) return RS_EINVAL;
+        model_host = reinterpret_cast<const float*>(static_cast<const char*>(model) + 4);
+    }
     PhaseParams pp;
+    pp.want_feat = (flags & RS_FEATURES) ? 1 : 0;
     pp.L = L;
     pp.h = 0.5f * L;
     pp.LQ = (int64_t)rint((double)L * 1048576.0);
@@ -431,8 +468,8 @@ int phase_run(const float* x, const float* y, const float* z, const float* vx,
     for (int attempt = 0; attempt < 8; attempt++) {
         bool overflow = false;
         rs_tree* t = nullptr;
-        RS_TRY(phase_attempt(x, y, z, vx, vy, vz, n, L, labels, min_group, pp, flags, cap, &t,
-                             &overflow, st));
+        RS_TRY(phase_attempt(x, y, z, vx, vy, vz, n, L, labels, min_group, pp, form, model_host,
+                             cap, &t, &overflow, st));
         if (!overflow) {
             *out = t;
             return RS_OK;

@@ -24,6 +24,7 @@ struct PhaseParams {
     int64_t LQ;        // rint(L * 2^20)
     int32_t min_sub;
     int64_t f_ppm;     // llround(f * 1e6)
+    int32_t want_feat; // compute proposer features for every node
 };
 
 // node record store (slots allocated by atomics, canonical order at the end)
@@ -33,6 +34,7 @@ struct NodeRec {
     int32_t* count;     // device counter of used slots
     int32_t cap;
     int32_t* overflow;  // set when a slot beyond cap was requested
+    float* feat;        // [cap * RS_NFEAT] proposer features, or NULL
 };
 
 // SoA member buffer
@@ -68,12 +70,15 @@ struct LItem {              // (node, chunk) work item
 struct LParam {
     float a, c, sa, sc;
     float rx, ry, rz;       // reference member position
-    float cx, cy, cz;       // mean position (for the sort key only)
-    float cu, cv, cw;       // mean velocity (sort key only)
+    float cx, cy, cz;       // mean position (sort key and feature centre)
+    float cu, cv, cw;       // mean velocity (sort key and feature centre)
     int32_t nowrap, cull;
     uint32_t pf, pm;        // radix-select prefix and mask
     int32_t kk;             // remaining rank
     float l2;
+    int32_t nnmode;         // 0 exact search, 1 bracket search, 2 done
+    float lo2, hi2;         // bracket (squares) when nnmode == 1
+    float isx, isv;         // 1/sigma_x, 1/sigma_v for the feature histograms
 };
 
 struct LCounters {
@@ -137,6 +142,12 @@ struct LargeWork {
     size_t sort_temp_bytes;
     TreeBuf tb;
     int32_t* root;
+    int32_t* lhist;      // [16 * cap_nodes] feature histograms
+    float* lfeat;        // [RS_NFEAT * cap_nodes] features of the level's large nodes
+    float* lnl;          // [cap_nodes] proposed ln(l)
+    int32_t* lcnt;       // [2 * cap_nodes] bracket counts #(<= lo), #(<= hi)
+    int32_t* lstat;      // [4] accepted, fell back
+    const float* model;  // device copy of the proposer, or NULL (exact search)
 };
 
 size_t large_work_bytes(int64_t m);
@@ -147,7 +158,8 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
 int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
                 const float* X, const float* Y, const float* Z, const PhaseParams& pp,
                 const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
-                hipStream_t st);
+                int64_t* n_accepted, int64_t* n_fallback, hipStream_t st);
+int mlp_infer(const float* model_dev, int nv, const float* feat, float* out, hipStream_t st);
 int run_small_bucket(int b, const SmallItem* items, int n_items, const Members& mb,
                      const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
                      hipStream_t st);
@@ -263,6 +275,65 @@ RS_DEV float phase_d2(float xi, float yi, float zi, float ui, float vi, float wi
                     : pos_d2_nowrap(xi, yi, zi, xj, yj, zj);
     float Dv = sum_sq3(ui - uj, vi - vj, wi - wj);
     return metric(a, Dx, c, Dv);
+}
+
+// ---------------------------------------------------------------------------
+// proposer features (see RS_NFEAT in rsfof.h)
+// ---------------------------------------------------------------------------
+
+RS_DEV int feat_bin(float t) {
+    return (t >= 0.25f) + (t >= 0.5f) + (t >= 0.75f) + (t >= 1.0f) + (t >= 1.5f) + (t >= 2.0f) +
+           (t >= 3.0f);
+}
+
+// centre and scale used for the histograms of one node
+struct FeatFrame {
+    float cx, cy, cz, cu, cv, cw;   // mean position (may lie outside the box) and velocity
+    float isx, isv;                 // 1/sigma (0 when sigma = 0)
+};
+
+RS_DEV FeatFrame feat_frame(const unsigned long long* acc, int64_t n, float rx, float ry,
+                            float rz, float sx2, float sv2) {
+    FeatFrame f;
+    double m[6];
+    for (int q = 0; q < 6; q++)
+        m[q] = (double)(int64_t)acc[q] / (double)n * (q < 3 ? 9.5367431640625e-07 : 9.765625e-4);
+    f.cx = (float)((double)rx + m[0]);
+    f.cy = (float)((double)ry + m[1]);
+    f.cz = (float)((double)rz + m[2]);
+    f.cu = (float)m[3];
+    f.cv = (float)m[4];
+    f.cw = (float)m[5];
+    f.isx = sx2 > 0.0f ? 1.0f / sqrtf(sx2) : 0.0f;
+    f.isv = sv2 > 0.0f ? 1.0f / sqrtf(sv2) : 0.0f;
+    return f;
+}
+
+RS_DEV void feat_member_bins(const FeatFrame& f, float x, float y, float z, float u, float v,
+                             float w, float L, float h, int* br, int* bv) {
+    float r2 = sum_sq3(min_image(x - f.cx, L, h), min_image(y - f.cy, L, h),
+                       min_image(z - f.cz, L, h));
+    float v2 = sum_sq3(u - f.cu, v - f.cv, w - f.cw);
+    *br = feat_bin(sqrtf(r2) * f.isx);
+    *bv = 8 + feat_bin(sqrtf(v2) * f.isv);
+}
+
+RS_DEV void feat_write(float* out, const unsigned long long* acc, int64_t n, int level,
+                       const int32_t* hist16) {
+    i128 t[6], Vx = 0, Vv = 0;
+    for (int q = 0; q < 6; q++) {
+        int64_t s1 = (int64_t)acc[q];
+        u128 s2 = ((u128)acc[7 + 2 * q] << 64) | (u128)acc[6 + 2 * q];
+        t[q] = (i128)n * (i128)s2 - (i128)s1 * (i128)s1;
+        if (q < 3) Vx += t[q]; else Vv += t[q];
+    }
+    out[0] = logf((float)n);
+    for (int q = 0; q < 3; q++) {
+        out[1 + q] = Vx > 0 ? (float)(i128_to_f64(t[q]) / i128_to_f64(Vx)) : (1.0f / 3.0f);
+        out[4 + q] = Vv > 0 ? (float)(i128_to_f64(t[3 + q]) / i128_to_f64(Vv)) : (1.0f / 3.0f);
+    }
+    for (int b = 0; b < 16; b++) out[7 + b] = (float)hist16[b] / (float)n;
+    out[23] = (float)level;
 }
 
 // lock-free union-find in LDS (same invariant as the global version)

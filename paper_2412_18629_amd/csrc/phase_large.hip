@@ -126,6 +126,11 @@ __global__ void k_lnorm(int nv, const LNode* __restrict__ nodes,
     P.pm = 0;
     P.kk = (int32_t)select_rank(nd.size, pp.f_ppm);
     P.l2 = 0.0f;
+    P.nnmode = 0;
+    P.lo2 = 0.0f;
+    P.hi2 = 0.0f;
+    P.isx = nm.sx2 > 0.0f ? 1.0f / sqrtf(nm.sx2) : 0.0f;
+    P.isv = nm.sv2 > 0.0f ? 1.0f / sqrtf(nm.sv2) : 0.0f;
     prm[v] = P;
     nr.a[nd.slot] = nm.a;
     nr.c[nd.slot] = nm.c;
@@ -483,6 +488,99 @@ __global__ void k_lscatter(int64_t m, const int32_t* __restrict__ par, Members T
     deepest[T.idx[t]] = s;
 }
 
+// ---------------------------------------------------------------------------
+// proposer features, proposal and exact acceptance of the bracket
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_lfeat(const LItem* __restrict__ items, Members in, const LParam* __restrict__ prm,
+        PhaseParams pp, int32_t* __restrict__ lhist) {
+    __shared__ int32_t hist[16];
+    const LItem it = items[blockIdx.x];
+    const LParam P = prm[it.v];
+    if (threadIdx.x < 16) hist[threadIdx.x] = 0;
+    __syncthreads();
+    FeatFrame f;
+    f.cx = P.cx; f.cy = P.cy; f.cz = P.cz; f.cu = P.cu; f.cv = P.cv; f.cw = P.cw;
+    f.isx = P.isx; f.isv = P.isv;
+    for (int j = threadIdx.x; j < it.len; j += 256) {
+        int64_t g = it.in_start + j;
+        int br, bv;
+        feat_member_bins(f, in.x[g], in.y[g], in.z[g], in.vx[g], in.vy[g], in.vz[g], pp.L, pp.h,
+                         &br, &bv);
+        atomicAdd(hist + br, 1);
+        atomicAdd(hist + bv, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && hist[threadIdx.x])
+        atomicAdd(lhist + 16 * it.v + threadIdx.x, hist[threadIdx.x]);
+}
+
+__global__ void k_lfeat_fin(int nv, const LNode* __restrict__ nodes,
+                            const unsigned long long* __restrict__ gacc,
+                            const int32_t* __restrict__ lhist, float* __restrict__ lfeat,
+                            NodeRec nr, int want_feat) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const LNode nd = nodes[v];
+    float* f = lfeat + (int64_t)v * RS_NFEAT;
+    feat_write(f, gacc + 18 * (int64_t)v, nd.size, nd.level, lhist + 16 * v);
+    if (want_feat)
+        for (int i = 0; i < RS_NFEAT; i++) nr.feat[(int64_t)nd.slot * RS_NFEAT + i] = f[i];
+}
+
+// bracket [0.95 l^, 1.05 l^] around the proposal, compared as squares
+__global__ void k_lbracket(int nv, const float* __restrict__ lnl, LParam* __restrict__ prm) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    float l = expf(lnl[v]);
+    if (!(l > 0.0f) || !(l < 3.0e18f)) {
+        prm[v].nnmode = 0;
+        return;
+    }
+    float lo = 0.95f * l, hi = 1.05f * l;
+    prm[v].lo2 = lo * lo;
+    prm[v].hi2 = hi * hi;
+    prm[v].nnmode = 1;
+}
+
+// #(d <= lo) and #(d <= hi) of bracket-mode nodes (d encoded by the search:
+// 0 = a neighbour within lo, exact in (lo, hi], +inf beyond hi)
+__global__ void __launch_bounds__(256)
+k_lcount(const LItem* __restrict__ items, const float* __restrict__ d2,
+         const LParam* __restrict__ prm, int32_t* __restrict__ lcnt) {
+    __shared__ int32_t c[2];
+    const LItem it = items[blockIdx.x];
+    if (prm[it.v].nnmode != 1) return;
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+    __syncthreads();
+    int a = 0, b = 0;
+    for (int j = threadIdx.x; j < it.len; j += 256) {
+        float d = d2[it.t_start + j];
+        a += d == 0.0f;
+        b += d < __builtin_huge_valf();
+    }
+    atomicAdd(c, a);
+    atomicAdd(c + 1, b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(lcnt + 2 * it.v, c[0]);
+        atomicAdd(lcnt + 2 * it.v + 1, c[1]);
+    }
+}
+
+// accept when #(<= lo) < k <= #(<= hi); otherwise the node is searched again
+// exactly (nnmode 0); accepted nodes are done (nnmode 2)
+__global__ void k_laccept(int nv, const int32_t* __restrict__ lcnt, LParam* __restrict__ prm,
+                          int32_t* __restrict__ lstat) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv || prm[v].nnmode != 1) return;
+    int k = prm[v].kk;
+    bool ok = lcnt[2 * v] < k && k <= lcnt[2 * v + 1];
+    prm[v].nnmode = ok ? 2 : 0;
+    atomicAdd(lstat + (ok ? 0 : 1), 1);
+}
+
 __global__ void k_lext_init(int nv, uint32_t* __restrict__ gext) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 6 * nv) gext[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
@@ -524,6 +622,7 @@ size_t large_work_bytes(int64_t m) {
     for (int k = 0; k < 5; k++) add(4 * cap_inode);            // tree internal nodes
     for (int k = 0; k < 3; k++) add(4 * cap_entry);            // tree entries
     add(4 * 16 * cap_entry); add(4 * m); add(64); add(4 * nodes);
+    add(4 * 16 * nodes); add(4 * RS_NFEAT * nodes); add(4 * nodes); add(4 * 2 * nodes); add(64);
     return b + 4096;
 }
 
@@ -590,7 +689,13 @@ int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
     tb.cap_inode = (int32_t)cap_inode;
     tb.cap_entry = (int32_t)cap_entry;
     w->root = take<int32_t>(ar, w->cap_nodes);
-    return (w->sort_temp && w->root) ? RS_OK : RS_EINTERNAL;
+    w->lhist = take<int32_t>(ar, 16 * w->cap_nodes);
+    w->lfeat = take<float>(ar, RS_NFEAT * w->cap_nodes);
+    w->lnl = take<float>(ar, w->cap_nodes);
+    w->lcnt = take<int32_t>(ar, 2 * w->cap_nodes);
+    w->lstat = take<int32_t>(ar, 16);
+    w->model = nullptr;
+    return (w->sort_temp && w->lstat) ? RS_OK : RS_EINTERNAL;
 }
 
 // Launches the small-subtree kernels over a device list of small items whose
@@ -618,7 +723,7 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
 int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
                 const float* X, const float* Y, const float* Z, const PhaseParams& pp,
                 const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
-                hipStream_t st) {
+                int64_t* n_accepted, int64_t* n_fallback, hipStream_t st) {
     const int nv = (int)hn.size();
     std::vector<LNode> nodes(nv);
     std::vector<LItem> items;
@@ -681,9 +786,42 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
                       &tree_levels, st));
     TArgs TA{w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
              8.0f * pp.L * 5.9604645e-08f};
+    // proposer features (when requested or when a proposal is wanted)
+    const bool learned = w->model != nullptr;
+    if (pp.want_feat || learned) {
+        RS_HIP(hipMemsetAsync(w->lhist, 0, 4 * 16 * (size_t)nv, st));
+        k_lfeat<<<ni, 256, 0, st>>>(w->items, in, w->prm, pp, w->lhist);
+        k_lfeat_fin<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->gacc, w->lhist, w->lfeat,
+                                                    nr, pp.want_feat);
+        RS_HIP(hipGetLastError());
+    }
+    if (learned) {
+        RS_TRY(mlp_infer(w->model, nv, w->lfeat, w->lnl, st));
+        k_lbracket<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->lnl, w->prm);
+        RS_HIP(hipGetLastError());
+    }
     prof_begin("phase_large_nn", st);
     RS_TRY(tree_nn(TA, tiles, w->d2, st));
     prof_end("phase_large_nn", st, (double)M);
+    if (learned) {
+        // exact acceptance of each bracket; rejected nodes are searched again
+        RS_HIP(hipMemsetAsync(w->lcnt, 0, 4 * 2 * (size_t)nv, st));
+        RS_HIP(hipMemsetAsync(w->lstat, 0, 4 * 4, st));
+        k_lcount<<<ni, 256, 0, st>>>(w->items, w->d2, w->prm, w->lcnt);
+        k_laccept<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->lcnt, w->prm, w->lstat);
+        RS_HIP(hipGetLastError());
+        int32_t* hs = nullptr;
+        RS_TRY(host_scratch((void**)&hs, 64));
+        RS_HIP(hipMemcpyAsync(hs, w->lstat, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+        *n_accepted += hs[0];
+        *n_fallback += hs[1];
+        if (hs[1] > 0) {
+            prof_begin("phase_large_nn_fallback", st);
+            RS_TRY(tree_nn(TA, tiles, w->d2, st));
+            prof_end("phase_large_nn_fallback", st, (double)M);
+        }
+    }
     for (int pass = 0; pass < 4; pass++) {
         int shift = 24 - 8 * pass;
         RS_HIP(hipMemsetAsync(w->ghist, 0, 4 * 256 * (size_t)nv, st));

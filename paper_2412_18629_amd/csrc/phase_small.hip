@@ -138,6 +138,8 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
                 Norm nm = mom_finalize(acc, sz);
                 shf[0] = nm.a;
                 shf[1] = nm.c;
+                shf[2] = nm.sx2;
+                shf[3] = nm.sv2;
                 bool nowrap = true;
 #pragma unroll
                 for (int ax = 0; ax < 3; ax++) {
@@ -153,6 +155,25 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             __syncthreads();
             const float fa = shf[0], fc = shf[1];
             const bool nowrap = sh[SH_NOWRAP] != 0;
+
+            // ---- proposer features (only when requested) ----
+            if (pp.want_feat) {
+                if (tid < 16) hist[tid] = 0;
+                __syncthreads();
+                const float4 pr = P[rslot];
+                const FeatFrame fr = feat_frame(acc, sz, pr.x, pr.y, pr.z, shf[2], shf[3]);
+                for (int m = tid; m < sz; m += NT) {
+                    int s = perm[s0 + m];
+                    float4 p = P[s], v = V[s];
+                    int br, bv;
+                    feat_member_bins(fr, p.x, p.y, p.z, v.x, v.y, v.z, pp.L, pp.h, &br, &bv);
+                    atomicAdd(hist + br, 1);
+                    atomicAdd(hist + bv, 1);
+                }
+                __syncthreads();
+                if (tid == 0) feat_write(nr.feat + (int64_t)slot * RS_NFEAT, acc, sz, level, hist);
+                __syncthreads();
+            }
 
             // ---- 2. nearest-neighbour distances ----
             {

@@ -308,19 +308,26 @@ __global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __re
     const int64_t ts = nd.t_off + 64ll * (t - nd.tile0);
     const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
     const bool cull = P.cull != 0;
+    if (P.nnmode == 2) return;               // bracket already accepted
+    // bracket mode: searches are capped at hi^2 and stop at the first
+    // neighbour within lo^2; the output encodes 0 = within lo, the exact d^2
+    // in (lo^2, hi^2], +inf = nothing within hi
+    const bool brk = P.nnmode == 1;
+    const float cap = brk ? __uint_as_float(__float_as_uint(P.hi2) + 1u) : __builtin_huge_valf();
+    const float lo2 = brk ? P.lo2 : -1.0f;
     const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
     for (int64_t qm = ts; qm < te; qm++) {
         const TQuery q = tq_load(T, qm, P, A.pp);
         const int32_t e0 = tb.leaf_of[qm];
         const int32_t* r0 = reinterpret_cast<const int32_t*>(tb.erec + 16 * (int64_t)e0);
-        float bl = __builtin_huge_valf();
+        float bl = cap;
         {
             const int64_t m = r0[12] + lane;
-            if (m < r0[13] && m != qm) bl = tq_d2(T, m, q, P, A.pp);
+            if (m < r0[13] && m != qm) bl = fminf(bl, tq_d2(T, m, q, P, A.pp));
         }
         float best = wmin(bl);
         if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
-        int sp = 1;
+        int sp = best <= lo2 ? 0 : 1;
         __syncthreads();
         while (sp > 0) {
             sp--;
@@ -370,10 +377,19 @@ __global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __re
                     }
                     bl = fminf(bl, fminf(fminf(d4[0], d4[1]), fminf(d4[2], d4[3])));
                     best = wmin(bl);
+                    if (best <= lo2) mk = 0;
+                }
+                if (best <= lo2) {
+                    sp = 0;
+                    break;
                 }
             }
         }
-        if (lane == 0) d2out[qm] = best;
+        if (lane == 0) {
+            float out = best;
+            if (brk) out = best <= lo2 ? 0.0f : (best <= P.hi2 ? best : __builtin_huge_valf());
+            d2out[qm] = out;
+        }
     }
 }
 
