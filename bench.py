@@ -6,7 +6,12 @@ timed region).  Prints one JSON line with the throughput, the roofline of the
 dominant kernel (HIP events recorded by the library on its launch stream)
 and the CPU oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form batched|plain]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form learned|batched|plain]
+
+The timed form is the learned one (the committed proposer); the line also
+reports the learned form's speed-up over the batched form on the same data
+and over the plain form (one group per launch sequence) on the 256^3
+workload, where one plain step takes seconds rather than minutes.
 """
 from __future__ import annotations
 
@@ -24,7 +29,7 @@ if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
 import paper_2412_18629_amd as rs  # noqa: E402
-from paper_2412_18629_amd import synth  # noqa: E402
+from paper_2412_18629_amd import learn, synth  # noqa: E402
 
 METRIC = "particles/s through 3D+6D FoF at 512³ (labels == oracle); learned vs plain speedup"
 HBM_PEAK_GBS = 8000.0
@@ -35,7 +40,9 @@ KERNEL_BYTES = {
     "phase_large_nn": 28.0,    # 24 B position+velocity in, 4 B d^2 out, per member
     "phase_large_link": 32.0,  # 24 B pos+vel + 4 B d^2 in, 4 B parent out, per member
     "phase_small": 32.0,       # 28 B member record in, 4 B deepest out, per member
+    "phase_large_nn_fallback": 28.0,
 }
+FLAGS = {"learned": rs.RS_LEARNED, "batched": rs.RS_BATCHED, "plain": rs.RS_PLAIN}
 
 
 def workload_description(cfg):
@@ -46,11 +53,35 @@ def workload_description(cfg):
             f"{cfg.min_group}/{cfg.min_sub}; seed 0")
 
 
-def one_step(arrs, cfg, flags, labels):
+def one_step(arrs, cfg, form, labels, model):
     x, y, z, vx, vy, vz = arrs
     rs.rs_fof3d(x, y, z, cfg.box, cfg.link_len, labels=labels)
     return rs.rs_phase_fof_batch(x, y, z, vx, vy, vz, cfg.box, labels, cfg.min_group,
-                                 cfg.min_sub, cfg.f, flags=flags)
+                                 cfg.min_sub, cfg.f, flags=FLAGS[form],
+                                 model=model if form == "learned" else None)
+
+
+def timed(fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / reps, out
+
+
+def speedups(arrs, cfg, labels, model, ms_learned):
+    """Learned over batched on the same data; learned over plain on 256^3."""
+    ms_b, _ = timed(lambda: one_step(arrs, cfg, "batched", labels, model))
+    c2 = synth.CONFIGS["c256"]
+    a2 = synth.generate(c2, 0, device=arrs[0].device)
+    l2 = torch.empty(c2.n, dtype=torch.int32, device=arrs[0].device)
+    one_step(a2, c2, "learned", l2, model)
+    ms_l2, _ = timed(lambda: one_step(a2, c2, "learned", l2, model), reps=2)
+    ms_p2, _ = timed(lambda: one_step(a2, c2, "plain", l2, model))
+    return {"vs_batched": ms_b / ms_learned, "batched_ms_per_step": ms_b,
+            "vs_plain": ms_p2 / ms_l2, "plain_workload": "c256 (256^3, 160 Mpc/h, seed 0)",
+            "plain_ms_per_step": ms_p2, "learned_ms_per_step_c256": ms_l2}
 
 
 def cpu_baseline(arrs, cfg, target=400000):
@@ -79,7 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c512")
-    ap.add_argument("--form", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--form", default="learned", choices=["learned", "batched", "plain"])
+    ap.add_argument("--no-speedup", action="store_true", help="skip the form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 3 times (a plain "
@@ -94,21 +126,21 @@ def main():
         return 2
     rs.load()
     cfg = synth.CONFIGS[args.config]
-    flags = {"batched": rs.RS_BATCHED, "plain": rs.RS_PLAIN}[args.form]
+    model = learn.load_model()
     dev = torch.device("cuda:0")
     arrs = synth.generate(cfg, 0, device=dev)
     labels = torch.empty(cfg.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
-        one_step(arrs, cfg, flags, labels)
+        one_step(arrs, cfg, args.form, labels, model)
     torch.cuda.synchronize()
 
     rs.rs_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        tree = one_step(arrs, cfg, flags, labels)
+        tree = one_step(arrs, cfg, args.form, labels, model)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {k: rs.rs_profile_get(k) for k in KERNEL_BYTES}
@@ -130,6 +162,8 @@ def main():
         "config": {"workload": workload_description(cfg), "form": args.form,
                    "groups": n_groups, "nodes": int(tree["level"].numel()),
                    "levels": tree["n_levels"],
+                   "proposals_accepted": tree["n_accepted"],
+                   "proposals_fallback": tree["n_fallback"],
                    "groups_per_s": n_groups / (ms / 1000.0),
                    "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -137,6 +171,8 @@ def main():
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    if args.form == "learned" and not args.no_speedup:
+        line["learned_speedup"] = speedups(arrs, cfg, labels, model, ms)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(arrs, cfg)
     if args.probe_copy > 0:

@@ -97,6 +97,7 @@ struct TreeBuf {
 };
 
 struct TArgs {
+    const int32_t* mnode;    // [members] node of each member (tile order)
     const int32_t* tile_node;
     const LNode* nodes;
     const LParam* prm;
@@ -112,6 +113,7 @@ int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* n
                const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st);
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st);
 int tree_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st);
+int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st);
 
 
 // device buffers of the large-node pipeline, sized by the level-0 total of

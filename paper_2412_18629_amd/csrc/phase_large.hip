@@ -784,7 +784,7 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     std::vector<int32_t> tree_levels;
     RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
                       &tree_levels, st));
-    TArgs TA{w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
+    TArgs TA{w->mnode, w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
              8.0f * pp.L * 5.9604645e-08f};
     // proposer features (when requested or when a proposal is wanted)
     const bool learned = w->model != nullptr;
@@ -831,7 +831,7 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     }
     k_liota<<<gm, BT, 0, st>>>(M, w->par);
     prof_begin("phase_large_link", st);
-    RS_TRY(tree_link(TA, tiles, w->d2, w->par, st));
+    RS_TRY(tile_link(TA, tiles, w->d2, w->par, st));
     prof_end("phase_large_link", st, (double)M);
     k_lflat<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk);
     k_lstat<<<gm, BT, 0, st>>>(M, w->par, w->T.idx, w->cnt, w->mpk);

@@ -27,7 +27,7 @@ size_t small_lds_bytes(int maxn, int min_sub) {
     return (size_t)maxn * 52 + (size_t)capn * 5 * 4 + (size_t)capn * 6 * 4 + 64;
 }
 
-template <int MAXN, int NT>
+template <int MAXN, int NT, bool FEAT>
 __global__ void __launch_bounds__(NT)
 k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, NodeRec nr,
                 PhaseParams pp, int32_t* __restrict__ deepest) {
@@ -157,7 +157,7 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             const bool nowrap = sh[SH_NOWRAP] != 0;
 
             // ---- proposer features (only when requested) ----
-            if (pp.want_feat) {
+            if (FEAT) {
                 if (tid < 16) hist[tid] = 0;
                 __syncthreads();
                 const float4 pr = P[rslot];
@@ -405,7 +405,7 @@ static int launch_small(const SmallItem* items, int n_items, const Members& mb,
                         hipStream_t st) {
     if (n_items <= 0) return RS_OK;
     size_t lds = small_lds_bytes(MAXN, pp.min_sub);
-    auto kern = k_small_subtree<MAXN, NT>;
+    auto kern = pp.want_feat ? k_small_subtree<MAXN, NT, true> : k_small_subtree<MAXN, NT, false>;
     RS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     unsigned grid = (unsigned)(n_items < (1 << 20) ? n_items : (1 << 20));

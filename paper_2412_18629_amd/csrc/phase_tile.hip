@@ -1,0 +1,192 @@
+// phase_tile.hip -- tile-cooperative searches over the 6D tree.
+//
+// One wavefront owns a tile of 64 consecutive members (one query per lane).
+// It walks the tree ONCE with the bounding box of its queries, collecting
+// every leaf that any query could need into an LDS list.  Each listed leaf
+// is then loaded once (one member per lane) and only the queries whose own
+// exact bound admits the leaf are replayed against it: each such query is
+// broadcast to the lanes, every lane evaluates the pair with its member.
+// Candidate data is read once per tile instead of once per query.
+#include "phase_common.h"
+
+namespace rs {
+
+constexpr int TSTACK = 520;   // >= 64 internal children x 8 levels
+constexpr int TLIST = 256;    // candidate leaves buffered before processing
+
+struct TileRec {
+    float lo[6], hi[6];
+    int32_t start, end, cfirst, ccount;
+};
+
+RS_DEV TileRec trec_load(const float* __restrict__ erec, int32_t k) {
+    const float4* p = reinterpret_cast<const float4*>(erec + 16 * (int64_t)k);
+    float4 a = p[0], b = p[1], c = p[2], d = p[3];
+    TileRec r;
+    r.lo[0] = a.x; r.lo[1] = a.y; r.lo[2] = a.z; r.lo[3] = a.w; r.lo[4] = b.x; r.lo[5] = b.y;
+    r.hi[0] = b.z; r.hi[1] = b.w; r.hi[2] = c.x; r.hi[3] = c.y; r.hi[4] = c.z; r.hi[5] = c.w;
+    r.start = __float_as_int(d.x);
+    r.end = __float_as_int(d.y);
+    r.cfirst = __float_as_int(d.z);
+    r.ccount = __float_as_int(d.w);
+    return r;
+}
+
+// exact lower bound of the computed d^2 between a point (w: unwrapped
+// position, u: velocity) or a box (wlo..whi, ulo..uhi) and a record's box;
+// position gaps lose an absolute slack covering the rounding of the
+// coordinates relative to the reference member, of the pair difference and
+// of the image shift; velocity gaps and the bound a relative margin
+RS_DEV float box_box_lb(const float blo[6], const float bhi[6], const TileRec& r, float a,
+                        float c, float slack) {
+    float sp = 0.0f, sv = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        float g = fmaxf(fmaxf(r.lo[d] - bhi[d], blo[d] - r.hi[d]), 0.0f);
+        g = fmaxf(g - slack, 0.0f);
+        sp += g * g;
+        float h = fmaxf(fmaxf(r.lo[3 + d] - bhi[3 + d], blo[3 + d] - r.hi[3 + d]), 0.0f) *
+                  0.99999905f;
+        sv += h * h;
+    }
+    return (a * sp + c * sv) * 0.99999f;
+}
+
+RS_DEV float tw_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+RS_DEV float tw_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct TStackEnt {
+    int32_t cfirst, ccount;
+};
+
+// Links within l among later members.  One wavefront per tile of 64
+// consecutive members of one node (tiles never straddle nodes).
+__global__ void __launch_bounds__(64)
+k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
+    __shared__ TStackEnt stk[TSTACK];
+    __shared__ int32_t list[TLIST];
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const TreeBuf& tb = A.tb;
+    const int v = A.tile_node[t];
+    const LNode nd = A.nodes[v];
+    const int64_t ts = nd.t_off + 64ll * (t - nd.tile0);
+    const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
+    const LParam P = A.prm[v];
+    const Members& T = A.T;
+    const PhaseParams& pp = A.pp;
+    const float l2 = P.l2;
+    const bool cull = P.cull != 0;
+
+    // this lane's query
+    const int64_t mq = ts + lane;
+    const bool valid = mq < te;
+    const int64_t mm = valid ? mq : ts;
+    const float qx = T.x[mm], qy = T.y[mm], qz = T.z[mm];
+    const float qu = T.vx[mm], qv = T.vy[mm], qw = T.vz[mm];
+    const bool act = valid && d2[mm] <= l2;
+    const uint64_t amask = __ballot(act);
+    if (!amask) return;
+    const float w[3] = {min_image(qx - P.rx, pp.L, pp.h), min_image(qy - P.ry, pp.L, pp.h),
+                        min_image(qz - P.rz, pp.L, pp.h)};
+    const float qpt[6] = {w[0], w[1], w[2], qu, qv, qw};
+    // box of the active queries
+    float blo[6], bhi[6];
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        blo[d] = tw_min(act ? qpt[d] : __builtin_huge_valf());
+        bhi[d] = tw_max(act ? qpt[d] : -__builtin_huge_valf());
+    }
+    const int64_t first_act = ts + __ffsll((unsigned long long)amask) - 1;
+
+    // one pass over the buffered candidate leaves: per leaf, the queries
+    // whose own bound admits it are replayed against its members
+    auto process = [&](int n) {
+        for (int li = 0; li < n; li++) {
+            const TileRec r = trec_load(tb.erec, list[li]);
+            bool need = act && r.end > mq + 1;
+            if (need && cull) need = !(box_box_lb(qpt, qpt, r, P.a, P.c, A.slack) > l2);
+            uint64_t mk = __ballot(need);
+            if (!mk) continue;
+            const int64_t mj = r.start + lane;
+            const bool has = mj < r.end;
+            const int64_t mjj = has ? mj : r.start;
+            const float xj = T.x[mjj], yj = T.y[mjj], zj = T.z[mjj];
+            const float uj = T.vx[mjj], vj = T.vy[mjj], wj = T.vz[mjj];
+            while (mk) {
+                const int src = __ffsll((unsigned long long)mk) - 1;
+                mk &= mk - 1;
+                const float bx = __shfl(qx, src, 64), by = __shfl(qy, src, 64),
+                            bz = __shfl(qz, src, 64);
+                const float bu = __shfl(qu, src, 64), bv = __shfl(qv, src, 64),
+                            bw = __shfl(qw, src, 64);
+                const int64_t mb = ts + src;
+                if (has && mj > mb) {
+                    float dd = P.nowrap
+                        ? phase_d2<false>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
+                                          P.c, pp.L, pp.h)
+                        : phase_d2<true>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
+                                         P.c, pp.L, pp.h);
+                    if (dd <= l2) uf_unite(par, (int)mb, (int)mj);
+                }
+            }
+        }
+    };
+
+    // walk the tree with the tile box; buffer leaves, flush when full
+    int nlist = 0;
+    if (lane == 0) stk[0] = TStackEnt{tb.cfirst[A.root[v]], tb.ccount[A.root[v]]};
+    int sp = 1;
+    __syncthreads();
+    while (sp > 0) {
+        sp--;
+        const TStackEnt se = stk[sp];
+        __syncthreads();
+        for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
+            const int32_t k = se.cfirst + b0 + lane;
+            bool need = false, leaf = false;
+            TileRec r;
+            r.cfirst = -1;
+            r.ccount = 0;
+            if (b0 + lane < se.ccount) {
+                r = trec_load(tb.erec, k);
+                leaf = r.cfirst < 0;
+                need = r.end > first_act + 1 &&
+                       (!cull || !(box_box_lb(blo, bhi, r, P.a, P.c, A.slack) > l2));
+            }
+            const uint64_t imask = __ballot(need && !leaf);
+            if (need && !leaf)
+                stk[sp + __popcll(imask & lanemask_lt())] = TStackEnt{r.cfirst, r.ccount};
+            sp += __popcll(imask);
+            const uint64_t lmask = __ballot(need && leaf);
+            if (nlist + __popcll(lmask) > TLIST) {
+                __syncthreads();
+                process(nlist);
+                nlist = 0;
+            }
+            if (need && leaf) list[nlist + __popcll(lmask & lanemask_lt())] = k;
+            nlist += __popcll(lmask);
+            __syncthreads();
+        }
+    }
+    process(nlist);
+}
+
+int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
+    if (ntiles <= 0) return RS_OK;
+    k_tile_link<<<ntiles, 64, 0, st>>>(A, ntiles, d2, par);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+}  // namespace rs
