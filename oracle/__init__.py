@@ -84,7 +84,7 @@ NODE_FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "s
 
 
 def phase_fof(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=0.7,
-              brute_max=3000):
+              brute_max=32):
     """Hierarchical 6D FoF.  Returns a dict of numpy arrays: the node fields
     in canonical (level, min_index) order, plus ``deepest`` per particle."""
     lib = _load()

@@ -27,9 +27,10 @@
  *   d^2 = fl( fl(a*Dx) + fl(c*Dv) ), Dv as D over velocity differences
  * Build with -ffp-contract=off -fno-fast-math.
  *
- * Acceleration structures (a position cell grid) only restrict which pairs
- * are evaluated; pruning uses lower bounds with a wide safety margin, and the
- * brute-force paths (all pairs) are kept and selectable for pinning.
+ * Acceleration structures (a 3D cell grid for the FoF pass, a 6D k-d tree
+ * inside nodes) only restrict which pairs are evaluated; pruning uses lower
+ * bounds with a wide safety margin, and the brute-force paths (all pairs)
+ * are kept and selectable for pinning.
  */
 #include <math.h>
 #include <stdint.h>
@@ -275,156 +276,184 @@ static norm_t node_norm(const parts_t *p, const int64_t *mem, int64_t n, int64_t
 }
 
 /* ------------------------------------------------------------------ */
-/* node-local position grid (fp64 unwrapped coordinates)               */
+/* node-local 6D k-d tree (fp64 unwrapped coordinates)                 */
 /* ------------------------------------------------------------------ */
 
-typedef struct {
-    int64_t g[3];           /* cells per axis */
-    double lo[3], cell;     /* grid origin and cell side */
-    int64_t *start;         /* [ncell + 1] */
-    int64_t *order;         /* member slots sorted by cell */
-    int64_t *cellof;        /* cell of each member slot */
-} grid_t;
+/*
+ * 6D k-d tree over one node's members: points are the positions unwrapped
+ * around the reference member (fp64, exact differences of fp32 values) and
+ * the raw velocities.  Each tree node covers a contiguous run of the slot
+ * permutation (the root all n slots, children the two halves at the median
+ * of the axis of largest metric-weighted extent) and stores the exact
+ * bounding box of its points.  Leaves hold at most KD_LEAF slots.
+ */
+#define KD_LEAF 8
 
-static void grid_free(grid_t *g)
+typedef struct {
+    int64_t n;
+    double *pt;          /* [n][6] */
+    int64_t *idx;        /* slot permutation */
+    double *box;         /* [nnode][12]: lo[6], hi[6] */
+    int64_t nnode;
+    float a, c;
+    double slack;        /* absolute slack on position gaps */
+} kd_t;
+
+static void kd_free(kd_t *t)
 {
-    free(g->start); free(g->order); free(g->cellof);
-    memset(g, 0, sizeof(*g));
+    free(t->pt); free(t->idx); free(t->box);
+    memset(t, 0, sizeof(*t));
 }
 
-/* Returns 0, or 1 if the node spans too much of the box for a grid. */
-static int grid_build(grid_t *g, const parts_t *p, const int64_t *mem, int64_t n,
-                      int64_t ref, double *ux, double *uy, double *uz)
+/* place the m-th smallest coordinate (axis dim) of idx[b..e) at m */
+static void kd_select(int64_t *idx, const double *pt, int dim, int64_t b, int64_t e, int64_t m)
 {
-    const float *pc[3] = { p->x, p->y, p->z };
-    double *u[3] = { ux, uy, uz };
-    double L = p->L, ext[3], hi[3];
-    memset(g, 0, sizeof(*g));
-    for (int a = 0; a < 3; a++) {
-        g->lo[a] = 1e300; hi[a] = -1e300;
+    while (e - b > 1) {
+        double v0 = pt[6 * idx[b] + dim], v1 = pt[6 * idx[b + (e - b) / 2] + dim],
+               v2 = pt[6 * idx[e - 1] + dim];
+        double piv = fmax(fmin(v0, v1), fmin(fmax(v0, v1), v2));   /* median of three */
+        int64_t lt = b, i = b, gt = e;
+        while (i < gt) {
+            double v = pt[6 * idx[i] + dim];
+            if (v < piv) { int64_t t = idx[lt]; idx[lt++] = idx[i]; idx[i++] = t; }
+            else if (v > piv) { int64_t t = idx[--gt]; idx[gt] = idx[i]; idx[i] = t; }
+            else i++;
+        }
+        if (m < lt) e = lt;
+        else if (m >= gt) b = gt;
+        else return;
+    }
+}
+
+static void kd_build_node(kd_t *t, int64_t k, int64_t b, int64_t e)
+{
+    double *bx = t->box + 12 * k;
+    for (int d = 0; d < 6; d++) { bx[d] = INFINITY; bx[6 + d] = -INFINITY; }
+    for (int64_t i = b; i < e; i++) {
+        const double *q = t->pt + 6 * t->idx[i];
+        for (int d = 0; d < 6; d++) {
+            if (q[d] < bx[d]) bx[d] = q[d];
+            if (q[d] > bx[6 + d]) bx[6 + d] = q[d];
+        }
+    }
+    if (e - b <= KD_LEAF) return;
+    int dim = 0;
+    double wmax = -1.0;
+    for (int d = 0; d < 6; d++) {
+        double w = (bx[6 + d] - bx[d]) * (d < 3 ? sqrt((double)t->a) : sqrt((double)t->c));
+        if (w > wmax) { wmax = w; dim = d; }
+    }
+    int64_t m = b + (e - b) / 2;
+    kd_select(t->idx, t->pt, dim, b, e, m);
+    kd_build_node(t, 2 * k + 1, b, m);
+    kd_build_node(t, 2 * k + 2, m, e);
+}
+
+/* Returns 0, or 1 if the node spans too much of the box for unwrapped
+   coordinates (then the caller uses all pairs), -3 on allocation failure. */
+static int kd_build(kd_t *t, const parts_t *p, const int64_t *mem, int64_t n, int64_t ref,
+                    float a, float c)
+{
+    const float *pc[6] = { p->x, p->y, p->z, p->vx, p->vy, p->vz };
+    double L = p->L;
+    memset(t, 0, sizeof(*t));
+    t->n = n; t->a = a; t->c = c;
+    t->slack = 8.0 * L * ldexp(1.0, -23);
+    int depth = 0;
+    while (((n + ((int64_t)1 << depth) - 1) >> depth) > KD_LEAF) depth++;
+    t->nnode = ((int64_t)1 << (depth + 1)) - 1;
+    t->pt = (double *)malloc(sizeof(double) * 6 * (size_t)n);
+    t->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    t->box = (double *)malloc(sizeof(double) * 12 * (size_t)t->nnode);
+    if (!t->pt || !t->idx || !t->box) { kd_free(t); return -3; }
+    for (int d = 0; d < 3; d++) {
+        double lo = INFINITY, hi = -INFINITY;
         for (int64_t m = 0; m < n; m++) {
-            double d = (double)pc[a][mem[m]] - (double)pc[a][ref];
-            if (d >= 0.5 * L) d -= L; else if (d < -0.5 * L) d += L;
-            u[a][m] = d;
-            if (d < g->lo[a]) g->lo[a] = d;
-            if (d > hi[a]) hi[a] = d;
+            double u = (double)pc[d][mem[m]] - (double)pc[d][ref];
+            if (u >= 0.5 * L) u -= L; else if (u < -0.5 * L) u += L;
+            t->pt[6 * m + d] = u;
+            if (u < lo) lo = u;
+            if (u > hi) hi = u;
         }
-        ext[a] = hi[a] - g->lo[a];
-        if (ext[a] > 0.25 * L) return 1;      /* near-percolating: brute force */
+        if (hi - lo > 0.25 * L) { kd_free(t); return 1; }
     }
-    double emax = fmax(ext[0], fmax(ext[1], ext[2]));
-    double per = cbrt((double)n / 8.0);
-    if (per < 1.0) per = 1.0;
-    g->cell = emax / per;
-    if (!(g->cell > 0.0)) g->cell = 1.0;
-    int64_t ncell;
-    for (;;) {
-        ncell = 1;
-        for (int a = 0; a < 3; a++) {
-            g->g[a] = (int64_t)floor(ext[a] / g->cell) + 1;
-            ncell *= g->g[a];
-        }
-        if (ncell <= 4 * n + 64) break;
-        g->cell *= 1.5;
-    }
-    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
-    g->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    g->cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    for (int64_t m = 0; m < n; m++) {
-        int64_t c[3];
-        for (int a = 0; a < 3; a++) {
-            c[a] = (int64_t)floor((u[a][m] - g->lo[a]) / g->cell);
-            if (c[a] >= g->g[a]) c[a] = g->g[a] - 1;
-            if (c[a] < 0) c[a] = 0;
-        }
-        g->cellof[m] = (c[2] * g->g[1] + c[1]) * g->g[0] + c[0];
-        g->start[g->cellof[m] + 1]++;
-    }
-    for (int64_t c = 0; c < ncell; c++) g->start[c + 1] += g->start[c];
-    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
-    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
-    for (int64_t m = 0; m < n; m++) g->order[fill[g->cellof[m]]++] = m;
-    free(fill);
+    for (int d = 3; d < 6; d++)
+        for (int64_t m = 0; m < n; m++) t->pt[6 * m + d] = (double)pc[d][mem[m]];
+    for (int64_t m = 0; m < n; m++) t->idx[m] = m;
+    kd_build_node(t, 0, 0, n);
     return 0;
 }
 
 /*
- * Lower bound on the computed a*Dx for any pair whose cells have at least r
- * whole cells between them along some axis, so that the true min-image
- * separation is >= r*cell.  1e-3 relative slack and an
- * absolute slack of 8 fp32 ulps of L cover all rounding of positions,
- * differences, squares and sums.
+ * Lower bound on the computed d^2 between point q and any member inside tree
+ * node k.  With the node extent below L/4 the unwrapped difference of two
+ * members is their minimum-image difference, so each axis gap bounds |dx|
+ * from below; position gaps lose an absolute slack (8 fp32 ulps of L) for
+ * the rounding of the coordinate differences and image shift, and the sum
+ * loses 1e-3 relative plus 1e-37 absolute for the rounding of squares, sums
+ * and products (including subnormal results).
  */
-static double ring_bound(const grid_t *g, const parts_t *p, int64_t r, double a)
+static double kd_lb(const kd_t *t, int64_t k, const double *q)
 {
-    double sep = (double)r * g->cell - 8.0 * (double)p->L * ldexp(1.0, -23);
-    if (sep <= 0.0) return 0.0;
-    return a * sep * sep * (1.0 - 1e-3);
+    const double *bx = t->box + 12 * k;
+    double sp = 0.0, sv = 0.0;
+    for (int d = 0; d < 6; d++) {
+        double g = fmax(fmax(bx[d] - q[d], q[d] - bx[6 + d]), 0.0);
+        if (d < 3) { g = fmax(g - t->slack, 0.0); sp += g * g; }
+        else sv += g * g;
+    }
+    return ((double)t->a * sp + (double)t->c * sv) * (1.0 - 1e-3) - 1e-37;
 }
 
-/* visit all member slots in the Chebyshev shell at distance r around cell c */
-typedef void (*visit_fn)(void *ctx, int64_t slot);
+typedef struct {
+    const kd_t *t;
+    const parts_t *p;
+    const int64_t *mem;
+    int64_t self;
+    const double *q;
+    float best;          /* nearest-neighbour search */
+    float l2;            /* linking */
+    int64_t *parent;
+} kd_query;
 
-static void visit_ring(const grid_t *g, int64_t cell, int64_t r, visit_fn fn, void *ctx)
+static void kd_nn(kd_query *s, int64_t k, int64_t b, int64_t e)
 {
-    int64_t cx = cell % g->g[0], cy = (cell / g->g[0]) % g->g[1], cz = cell / (g->g[0] * g->g[1]);
-    for (int64_t dz = -r; dz <= r; dz++) {
-        int64_t z = cz + dz;
-        if (z < 0 || z >= g->g[2]) continue;
-        for (int64_t dy = -r; dy <= r; dy++) {
-            int64_t y = cy + dy;
-            if (y < 0 || y >= g->g[1]) continue;
-            int64_t adz = dz < 0 ? -dz : dz, ady = dy < 0 ? -dy : dy;
-            int on_face = (adz == r || ady == r);
-            for (int64_t dx = -r; dx <= r; dx++) {
-                int64_t adx = dx < 0 ? -dx : dx;
-                if (!on_face && adx != r) continue;
-                int64_t x = cx + dx;
-                if (x < 0 || x >= g->g[0]) continue;
-                int64_t c = (z * g->g[1] + y) * g->g[0] + x;
-                for (int64_t q = g->start[c]; q < g->start[c + 1]; q++) fn(ctx, g->order[q]);
-            }
+    if (kd_lb(s->t, k, s->q) >= (double)s->best) return;
+    if (e - b <= KD_LEAF) {
+        for (int64_t i = b; i < e; i++) {
+            int64_t j = s->t->idx[i];
+            if (j == s->self) continue;
+            float d = phase_d2(s->p, s->mem[s->self], s->mem[j], s->t->a, s->t->c);
+            if (d < s->best) s->best = d;
         }
+        return;
+    }
+    int64_t m = b + (e - b) / 2;
+    if (kd_lb(s->t, 2 * k + 1, s->q) <= kd_lb(s->t, 2 * k + 2, s->q)) {
+        kd_nn(s, 2 * k + 1, b, m);
+        kd_nn(s, 2 * k + 2, m, e);
+    } else {
+        kd_nn(s, 2 * k + 2, m, e);
+        kd_nn(s, 2 * k + 1, b, m);
     }
 }
 
-static int64_t grid_max_ring(const grid_t *g)
+/* unions the query with every later slot within l^2 */
+static void kd_link(kd_query *s, int64_t k, int64_t b, int64_t e)
 {
-    int64_t m = g->g[0];
-    if (g->g[1] > m) m = g->g[1];
-    if (g->g[2] > m) m = g->g[2];
-    return m;
-}
-
-typedef struct {
-    const parts_t *p;
-    const int64_t *mem;
-    int64_t self;
-    float a, c, best;
-} nn_ctx;
-
-static void nn_visit(void *vctx, int64_t slot)
-{
-    nn_ctx *q = (nn_ctx *)vctx;
-    if (slot == q->self) return;
-    float d = phase_d2(q->p, q->mem[q->self], q->mem[slot], q->a, q->c);
-    if (d < q->best) q->best = d;
-}
-
-typedef struct {
-    const parts_t *p;
-    const int64_t *mem;
-    int64_t self;
-    float a, c, l2;
-    int64_t *parent;
-} link_ctx;
-
-static void link_visit(void *vctx, int64_t slot)
-{
-    link_ctx *q = (link_ctx *)vctx;
-    if (slot <= q->self) return;
-    if (phase_d2(q->p, q->mem[q->self], q->mem[slot], q->a, q->c) <= q->l2)
-        uf_union(q->parent, q->self, slot);
+    if (kd_lb(s->t, k, s->q) > (double)s->l2) return;
+    if (e - b <= KD_LEAF) {
+        for (int64_t i = b; i < e; i++) {
+            int64_t j = s->t->idx[i];
+            if (j <= s->self) continue;
+            if (phase_d2(s->p, s->mem[s->self], s->mem[j], s->t->a, s->t->c) <= s->l2)
+                uf_union(s->parent, s->self, j);
+        }
+        return;
+    }
+    int64_t m = b + (e - b) / 2;
+    kd_link(s, 2 * k + 1, b, m);
+    kd_link(s, 2 * k + 2, m, e);
 }
 
 static int cmp_f32(const void *pa, const void *pb)
@@ -472,12 +501,6 @@ static int nv_push(nodevec *nv, node_t nd)
     return 0;
 }
 
-static int cmp_i64(const void *pa, const void *pb)
-{
-    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    return (a > b) - (a < b);
-}
-
 /*
  * Split one node: fills its l2/a/c/sigma fields and appends its children
  * (with member lists in ascending index order) to the node vector.
@@ -494,12 +517,14 @@ static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub
 
     float *d2 = (float *)malloc(sizeof(float) * (size_t)n);
     int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    double *ux = (double *)malloc(sizeof(double) * (size_t)n * 3);
-    if (!d2 || !parent || !ux) { free(d2); free(parent); free(ux); return -3; }
+    if (!d2 || !parent) { free(d2); free(parent); return -3; }
 
-    grid_t g;
+    kd_t t;
     int brute = (n <= brute_max);
-    if (!brute) brute = grid_build(&g, p, mem, n, mem[0], ux, ux + n, ux + 2 * n);
+    if (!brute) {
+        brute = kd_build(&t, p, mem, n, mem[0], a, c);
+        if (brute < 0) { free(d2); free(parent); return -3; }
+    }
 
     /* nearest-neighbour distance of every member */
     if (brute) {
@@ -513,14 +538,9 @@ static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub
             d2[i] = best;
         }
     } else {
-        int64_t rmax = grid_max_ring(&g);
         for (int64_t i = 0; i < n; i++) {
-            nn_ctx q = { p, mem, i, a, c, INFINITY };
-            for (int64_t r = 0; r <= rmax; r++) {
-                /* cells r rings away are separated by >= r-1 whole cells */
-                if (r >= 1 && ring_bound(&g, p, r - 1, (double)a) > (double)q.best) break;
-                visit_ring(&g, g.cellof[i], r, nn_visit, &q);
-            }
+            kd_query q = { &t, p, mem, i, t.pt + 6 * i, INFINITY, 0.0f, NULL };
+            kd_nn(&q, 0, 0, n);
             d2[i] = q.best;
         }
     }
@@ -540,16 +560,12 @@ static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub
             for (int64_t j = i + 1; j < n; j++)
                 if (phase_d2(p, mem[i], mem[j], a, c) <= l2) uf_union(parent, i, j);
     } else {
-        int64_t rmax = grid_max_ring(&g);
         for (int64_t i = 0; i < n; i++) {
             if (!(d2[i] <= l2)) continue;            /* no neighbour within l: cannot link */
-            link_ctx q = { p, mem, i, a, c, l2, parent };
-            for (int64_t r = 0; r <= rmax; r++) {
-                if (r >= 1 && ring_bound(&g, p, r - 1, (double)a) > (double)l2) break;
-                visit_ring(&g, g.cellof[i], r, link_visit, &q);
-            }
+            kd_query q = { &t, p, mem, i, t.pt + 6 * i, INFINITY, l2, parent };
+            kd_link(&q, 0, 0, n);
         }
-        grid_free(&g);
+        kd_free(&t);
     }
 
     nv->v[id].l2 = l2; nv->v[id].a = a; nv->v[id].c = c;
@@ -574,7 +590,7 @@ static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub
             if (uf_find(parent, i) == r) ch.mem[w++] = mem[i];
         rc = nv_push(nv, ch);
     }
-    free(count); free(d2); free(parent); free(ux);
+    free(count); free(d2); free(parent);
     return rc;
 }
 

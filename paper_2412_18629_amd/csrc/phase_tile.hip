@@ -68,6 +68,11 @@ struct TStackEnt {
     int32_t cfirst, ccount;
 };
 
+// value of lane src (uniform) in every lane, through the scalar unit
+RS_DEV float bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Links within l among later members.  One wavefront per tile of 64
 // consecutive members of one node (tiles never straddle nodes).
 __global__ void __launch_bounds__(64)
@@ -126,10 +131,8 @@ k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restri
             while (mk) {
                 const int src = __ffsll((unsigned long long)mk) - 1;
                 mk &= mk - 1;
-                const float bx = __shfl(qx, src, 64), by = __shfl(qy, src, 64),
-                            bz = __shfl(qz, src, 64);
-                const float bu = __shfl(qu, src, 64), bv = __shfl(qv, src, 64),
-                            bw = __shfl(qw, src, 64);
+                const float bx = bcast(qx, src), by = bcast(qy, src), bz = bcast(qz, src);
+                const float bu = bcast(qu, src), bv = bcast(qv, src), bw = bcast(qw, src);
                 const int64_t mb = ts + src;
                 if (has && mj > mb) {
                     float dd = P.nowrap

@@ -1,0 +1,64 @@
+"""Parity at full workload size, run the way the benchmark runs it.
+
+The 512^3 workload (134M particles, 150k NFW hosts) goes through rs_fof3d and
+the learned 6D form with the shipped proposer on the current stream, exactly
+as bench.py times it; the 256^3 workload goes through the plain form.  The
+oracle cannot redo a whole 512^3 box inside a test, so the result is checked
+in parts it computes one at a time, plus properties that hold at any size
+(tests/fullsize_checks.py):
+
+  * every level-0 node: (a, c, sigma_x^2, sigma_v^2) equal the oracle's
+    moments of its member set, for all groups;
+  * the whole tree: canonical order, parent levels, sizes as the sum of own
+    and child members, deepest[] consistent, level-0 nodes = the 3D groups of
+    at least min_group members;
+  * 64 3D groups sampled across 10 log-size bins: closed and connected, by
+    the oracle FoF of the group's bounding region grown by ll;
+  * the 6D subtree of each sampled group up to 500k members: the oracle's
+    hierarchy of that member set, field by field.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2412_18629_amd as rs
+from paper_2412_18629_amd import learn, synth
+
+from fullsize_checks import FIELDS, check_all
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cfg, form):
+    dev = torch.device("cuda:0")
+    arrs = synth.generate(cfg, 0, device=dev)
+    labels = torch.empty(cfg.n, dtype=torch.int32, device=dev)
+    rs.rs_fof3d(*arrs[:3], cfg.box, cfg.link_len, labels=labels)
+    flags = {"learned": rs.RS_LEARNED, "plain": rs.RS_PLAIN}[form]
+    tree = rs.rs_phase_fof_batch(*arrs, cfg.box, labels, cfg.min_group, cfg.min_sub, cfg.f,
+                                 flags=flags,
+                                 model=learn.load_model() if form == "learned" else None)
+    torch.cuda.synchronize()
+    sl, order = torch.sort(labels.long(), stable=True)
+    nc = int(cfg.box // 2.0)
+    side = cfg.box / nc
+    cell = [torch.clamp((a.double() / side).floor().long(), 0, nc - 1) for a in arrs[:3]]
+    key = (cell[0] * nc + cell[1]) * nc + cell[2]
+    ks, cperm = torch.sort(key, stable=True)
+    cstart = torch.searchsorted(ks, torch.arange(nc ** 3 + 1, device=dev))
+    R = dict(host=[a.cpu().numpy() for a in arrs], labels=labels.cpu().numpy(),
+             order=order.cpu().numpy(), sorted_labels=sl.cpu().numpy(),
+             cperm=cperm.cpu().numpy(), cstart=cstart.cpu().numpy(), nc=nc, side=side,
+             tree={k: tree[k].cpu().numpy() for k in FIELDS + ("deepest",)})
+    del arrs, labels, tree, sl, order, cell, key, ks, cperm, cstart
+    torch.cuda.empty_cache()
+    return R
+
+
+@pytest.mark.timeout(1500)
+@pytest.mark.parametrize("config,form", [("c512", "learned"), ("c256", "plain")])
+def test_fullsize_sampled_parity(config, form):
+    cfg = synth.CONFIGS[config]
+    R = _run(cfg, form)
+    n3, n6 = check_all(R, cfg, subtree_max=500000, log=lambda s: print(s, flush=True))
+    assert n3 >= 60 and n6 >= 55
