@@ -106,13 +106,47 @@ struct TArgs {
     Members T;
     PhaseParams pp;
     float slack;
+    int64_t nmem;            // members at this level
 };
+
+// A member's coordinate.  With O32 (fewer than 2^30 members) the byte offset
+// is formed in 32 bits, so the six loads of one member share one offset
+// register and address from the uniform array bases.
+template <bool O32>
+RS_DEV float mload(const float* __restrict__ base, int64_t m) {
+    if constexpr (O32)
+        return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) +
+                                               ((uint32_t)m << 2));
+    else
+        return base[m];
+}
+constexpr int64_t O32_LIMIT = (int64_t)1 << 30;
 
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,
                const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st);
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Blocks are remapped so that every XCD runs consecutive chunks of C
+// tiles: neighbouring tiles, which read mostly the same candidate data, then
+// share one L2.  The grid is rounded up to whole rounds of 8*C blocks; the
+// mapping is a bijection on the rounded range, and blocks whose tile index
+// is past the end exit.
+constexpr int XCDS = 8;
+RS_DEV int xcd_chunk_index(int b, int C) {
+    const int x = b % XCDS, r = b / XCDS;
+    return ((r / C) * XCDS + x) * C + r % C;
+}
+inline int xcd_chunk_grid(int n, int C) {
+    const int g = XCDS * C;
+    return (n + g - 1) / g * g;
+}
+// chunk length: whole rounds stay at least 64 so the XCDs finish together
+inline int xcd_chunk(int ntiles) {
+    int c = ntiles / (64 * XCDS);
+    return c < 1 ? 1 : (c > 1024 ? 1024 : c);
+}
+
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st);
-int tree_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st);
 int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st);
 
 

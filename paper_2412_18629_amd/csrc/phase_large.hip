@@ -785,7 +785,7 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
                       &tree_levels, st));
     TArgs TA{w->mnode, w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
-             8.0f * pp.L * 5.9604645e-08f};
+             8.0f * pp.L * 5.9604645e-08f, M};
     // proposer features (when requested or when a proposal is wanted)
     const bool learned = w->model != nullptr;
     if (pp.want_feat || learned) {

@@ -75,12 +75,14 @@ RS_DEV float bcast(float v, int src) {
 
 // Links within l among later members.  One wavefront per tile of 64
 // consecutive members of one node (tiles never straddle nodes).
+template <bool O32>
 __global__ void __launch_bounds__(64)
-k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
+k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
+            int32_t* __restrict__ par) {
     __shared__ TStackEnt stk[TSTACK];
     __shared__ int32_t list[TLIST];
     const int lane = threadIdx.x;
-    const int t = blockIdx.x;
+    const int t = xcd_chunk_index(blockIdx.x, chunk);
     if (t >= ntiles) return;
     const TreeBuf& tb = A.tb;
     const int v = A.tile_node[t];
@@ -97,9 +99,9 @@ k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restri
     const int64_t mq = ts + lane;
     const bool valid = mq < te;
     const int64_t mm = valid ? mq : ts;
-    const float qx = T.x[mm], qy = T.y[mm], qz = T.z[mm];
-    const float qu = T.vx[mm], qv = T.vy[mm], qw = T.vz[mm];
-    const bool act = valid && d2[mm] <= l2;
+    const float qx = mload<O32>(T.x, mm), qy = mload<O32>(T.y, mm), qz = mload<O32>(T.z, mm);
+    const float qu = mload<O32>(T.vx, mm), qv = mload<O32>(T.vy, mm), qw = mload<O32>(T.vz, mm);
+    const bool act = valid && mload<O32>(d2, mm) <= l2;
     const uint64_t amask = __ballot(act);
     if (!amask) return;
     const float w[3] = {min_image(qx - P.rx, pp.L, pp.h), min_image(qy - P.ry, pp.L, pp.h),
@@ -126,8 +128,10 @@ k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restri
             const int64_t mj = r.start + lane;
             const bool has = mj < r.end;
             const int64_t mjj = has ? mj : r.start;
-            const float xj = T.x[mjj], yj = T.y[mjj], zj = T.z[mjj];
-            const float uj = T.vx[mjj], vj = T.vy[mjj], wj = T.vz[mjj];
+            const float xj = mload<O32>(T.x, mjj), yj = mload<O32>(T.y, mjj),
+                        zj = mload<O32>(T.z, mjj);
+            const float uj = mload<O32>(T.vx, mjj), vj = mload<O32>(T.vy, mjj),
+                        wj = mload<O32>(T.vz, mjj);
             while (mk) {
                 const int src = __ffsll((unsigned long long)mk) - 1;
                 mk &= mk - 1;
@@ -187,7 +191,11 @@ k_tile_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restri
 
 int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
     if (ntiles <= 0) return RS_OK;
-    k_tile_link<<<ntiles, 64, 0, st>>>(A, ntiles, d2, par);
+    const int c = xcd_chunk(ntiles);
+    if (A.nmem < O32_LIMIT)
+        k_tile_link<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);
+    else
+        k_tile_link<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }

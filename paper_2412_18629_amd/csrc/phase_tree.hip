@@ -144,6 +144,22 @@ RS_DEV float wmax(float v) {
     return v;
 }
 
+// minimum over the 64 lanes of a non-negative float (or +inf), returned
+// uniform; non-negative float bit patterns order like their values.  Row
+// steps (quad permutes, row rotations) leave each 16-lane row's minimum in
+// all its lanes; two row broadcasts carry it to lane 63.  All 64 lanes must
+// be active.
+RS_DEV float wmin_nonneg(float x) {
+    uint32_t v = __float_as_uint(x);
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xa, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xc, 0xf, false));
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
+}
+
 // leaf boxes (wave per entry) and the leaf of every member
 __global__ void __launch_bounds__(256)
 k_tree_leafbox(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict__ mnode,
@@ -242,9 +258,11 @@ RS_DEV TQuery tq_load(const Members& T, int64_t m, const LParam& P, const PhaseP
     return q;
 }
 
+template <bool O32>
 RS_DEV float tq_d2(const Members& T, int64_t m, const TQuery& q, const LParam& P,
                    const PhaseParams& pp) {
-    float xj = T.x[m], yj = T.y[m], zj = T.z[m], uj = T.vx[m], vj = T.vy[m], wj = T.vz[m];
+    const float xj = mload<O32>(T.x, m), yj = mload<O32>(T.y, m), zj = mload<O32>(T.z, m);
+    const float uj = mload<O32>(T.vx, m), vj = mload<O32>(T.vy, m), wj = mload<O32>(T.vz, m);
     return P.nowrap
         ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h)
         : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h);
@@ -295,10 +313,12 @@ struct StackEnt {
 // depth-first descent from the node's root.  One wavefront per tile of
 // queries, one query at a time; child records are bounded lane-parallel,
 // surviving leaves are scanned four at a time with independent loads.
-__global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __restrict__ d2out) {
+template <bool O32>
+__global__ void __launch_bounds__(64)
+k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
     __shared__ StackEnt stk[STACK_PER_WAVE];
     const int lane = threadIdx.x;
-    const int t = blockIdx.x;
+    const int t = xcd_chunk_index(blockIdx.x, chunk);
     if (t >= ntiles) return;
     const int v = A.tile_node[t];
     const LNode nd = A.nodes[v];
@@ -323,9 +343,9 @@ __global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __re
         float bl = cap;
         {
             const int64_t m = r0[12] + lane;
-            if (m < r0[13] && m != qm) bl = fminf(bl, tq_d2(T, m, q, P, A.pp));
+            if (m < r0[13] && m != qm) bl = fminf(bl, tq_d2<O32>(T, m, q, P, A.pp));
         }
-        float best = wmin(bl);
+        float best = wmin_nonneg(bl);
         if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
         int sp = best <= lo2 ? 0 : 1;
         __syncthreads();
@@ -356,27 +376,51 @@ __global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __re
                 __syncthreads();
                 uint64_t mk = __ballot(need && leaf);
                 while (mk) {
-                    // up to four leaves: member loads issued together
+                    // up to four leaves: every lane loads one member of each
+                    // (a valid member where the leaf is shorter, masked
+                    // afterwards), all loads before any arithmetic so that
+                    // they are in flight together
                     int32_t s4[4], e4[4];
+                    int cnt = 0;
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
+                        s4[j] = e4[j] = 0;
                         if (mk) {
                             const int src = __ffsll((unsigned long long)mk) - 1;
                             mk &= mk - 1;
-                            s4[j] = __shfl(r.start, src, 64);
-                            e4[j] = __shfl(r.end, src, 64);
-                        } else {
-                            s4[j] = e4[j] = 0;
+                            s4[j] = __builtin_amdgcn_readlane(r.start, src);
+                            e4[j] = __builtin_amdgcn_readlane(r.end, src);
+                            cnt++;
+                        }
+                    }
+                    float mx[4], my[4], mz[4], mu[4], mv[4], mw[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        mx[j] = my[j] = mz[j] = mu[j] = mv[j] = mw[j] = 0.0f;
+                        if (j < cnt) {
+                            const int64_t m = s4[j] + lane < e4[j] ? s4[j] + lane : qm;
+                            mx[j] = mload<O32>(T.x, m); my[j] = mload<O32>(T.y, m);
+                            mz[j] = mload<O32>(T.z, m); mu[j] = mload<O32>(T.vx, m);
+                            mv[j] = mload<O32>(T.vy, m); mw[j] = mload<O32>(T.vz, m);
                         }
                     }
                     float d4[4];
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
-                        const int64_t m = s4[j] + lane;
-                        d4[j] = m < e4[j] ? tq_d2(T, m, q, P, A.pp) : __builtin_huge_valf();
+                        d4[j] = __builtin_huge_valf();
+                        if (j < cnt) {
+                            const float d = P.nowrap
+                                ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, mx[j], my[j],
+                                                  mz[j], mu[j], mv[j], mw[j], P.a, P.c, A.pp.L,
+                                                  A.pp.h)
+                                : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, mx[j], my[j],
+                                                 mz[j], mu[j], mv[j], mw[j], P.a, P.c, A.pp.L,
+                                                 A.pp.h);
+                            if (s4[j] + lane < e4[j]) d4[j] = d;
+                        }
                     }
                     bl = fminf(bl, fminf(fminf(d4[0], d4[1]), fminf(d4[2], d4[3])));
-                    best = wmin(bl);
+                    best = wmin_nonneg(bl);
                     if (best <= lo2) mk = 0;
                 }
                 if (best <= lo2) {
@@ -389,90 +433,6 @@ __global__ void __launch_bounds__(64) k_tree_nn(TArgs A, int ntiles, float* __re
             float out = best;
             if (brk) out = best <= lo2 ? 0.0f : (best <= P.hi2 ? best : __builtin_huge_valf());
             d2out[qm] = out;
-        }
-    }
-}
-
-// links within l against later members (member index > query): own leaf,
-// then a descent that prunes boxes farther than l and subtrees that hold no
-// later member; leaves scanned four at a time
-__global__ void __launch_bounds__(64)
-k_tree_link(TArgs A, int ntiles, const float* __restrict__ d2, int32_t* __restrict__ par) {
-    __shared__ StackEnt stk[STACK_PER_WAVE];
-    const int lane = threadIdx.x;
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
-    const int v = A.tile_node[t];
-    const LNode nd = A.nodes[v];
-    const LParam P = A.prm[v];
-    const Members& T = A.T;
-    const TreeBuf& tb = A.tb;
-    const int64_t ts = nd.t_off + 64ll * (t - nd.tile0);
-    const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
-    const bool cull = P.cull != 0;
-    const float l2 = P.l2;
-    const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
-    for (int64_t qm = ts; qm < te; qm++) {
-        if (!(d2[qm] <= l2)) continue;
-        const TQuery q = tq_load(T, qm, P, A.pp);
-        const int32_t e0 = tb.leaf_of[qm];
-        const int32_t* r0 = reinterpret_cast<const int32_t*>(tb.erec + 16 * (int64_t)e0);
-        {
-            const int64_t m = r0[12] + lane;
-            if (m < r0[13] && m > qm && tq_d2(T, m, q, P, A.pp) <= l2)
-                uf_unite(par, (int)qm, (int)m);
-        }
-        if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
-        int sp = 1;
-        __syncthreads();
-        while (sp > 0) {
-            sp--;
-            const StackEnt se = stk[sp];
-            __syncthreads();
-            for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
-                const int32_t k = se.cfirst + b0 + lane;
-                Rec r;
-                bool need = false;
-                if (b0 + lane < se.ccount && k != e0) {
-                    r = rec_load(tb.erec, k);
-                    need = r.end > qm + 1 &&
-                           (!cull || !(rec_lb(r, q, P.a, P.c, A.slack) > l2));
-                } else {
-                    r.start = r.end = 0;
-                    r.cfirst = -1;
-                    r.ccount = 0;
-                }
-                const bool leaf = r.cfirst < 0;
-                const uint64_t imask = __ballot(need && !leaf);
-                if (need && !leaf)
-                    stk[sp + __popcll(imask & lanemask_lt())] = StackEnt{r.cfirst, r.ccount, 0.0f};
-                sp += __popcll(imask);
-                __syncthreads();
-                uint64_t mk = __ballot(need && leaf);
-                while (mk) {
-                    int32_t s4[4], e4[4];
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        if (mk) {
-                            const int src = __ffsll((unsigned long long)mk) - 1;
-                            mk &= mk - 1;
-                            s4[j] = __shfl(r.start, src, 64);
-                            e4[j] = __shfl(r.end, src, 64);
-                        } else {
-                            s4[j] = e4[j] = 0;
-                        }
-                    }
-                    bool hit[4];
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        const int64_t m = s4[j] + lane;
-                        hit[j] = m < e4[j] && m > qm && tq_d2(T, m, q, P, A.pp) <= l2;
-                    }
-#pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        if (hit[j]) uf_unite(par, (int)qm, (int)(s4[j] + lane));
-                }
-            }
         }
     }
 }
@@ -537,13 +497,11 @@ int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* n
 }
 
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st) {
-    k_tree_nn<<<ntiles, 64, 0, st>>>(A, ntiles, d2);
-    RS_HIP(hipGetLastError());
-    return RS_OK;
-}
-
-int tree_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
-    k_tree_link<<<ntiles, 64, 0, st>>>(A, ntiles, d2, par);
+    const int c = xcd_chunk(ntiles);
+    if (A.nmem < O32_LIMIT)
+        k_tree_nn<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
+    else
+        k_tree_nn<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
