@@ -76,7 +76,7 @@ struct LParam {
     uint32_t pf, pm;        // radix-select prefix and mask
     int32_t kk;             // remaining rank
     float l2;
-    int32_t nnmode;         // 0 exact search, 1 bracket search, 2 done
+    int32_t nnmode;         // 0 exact, 1 bracket, 2 done, 3/4 refine below lo / above hi
     float lo2, hi2;         // bracket (squares) when nnmode == 1
     float isx, isv;         // 1/sigma_x, 1/sigma_v for the feature histograms
 };

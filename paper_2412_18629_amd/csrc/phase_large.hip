@@ -569,15 +569,17 @@ k_lcount(const LItem* __restrict__ items, const float* __restrict__ d2,
     }
 }
 
-// accept when #(<= lo) < k <= #(<= hi); otherwise the node is searched again
-// exactly (nnmode 0); accepted nodes are done (nnmode 2)
+// accept when #(<= lo) < k <= #(<= hi) (nnmode 2: done); otherwise the
+// queries that can hold the k-th value are searched again exactly: those
+// within lo when k <= #(<= lo) (nnmode 3), those beyond hi when
+// k > #(<= hi) (nnmode 4)
 __global__ void k_laccept(int nv, const int32_t* __restrict__ lcnt, LParam* __restrict__ prm,
                           int32_t* __restrict__ lstat) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv || prm[v].nnmode != 1) return;
     int k = prm[v].kk;
     bool ok = lcnt[2 * v] < k && k <= lcnt[2 * v + 1];
-    prm[v].nnmode = ok ? 2 : 0;
+    prm[v].nnmode = ok ? 2 : (k <= lcnt[2 * v] ? 3 : 4);
     atomicAdd(lstat + (ok ? 0 : 1), 1);
 }
 

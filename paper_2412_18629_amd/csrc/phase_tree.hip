@@ -329,14 +329,23 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
     const int64_t te = min(ts + 64, nd.t_off + (int64_t)nd.size);
     const bool cull = P.cull != 0;
     if (P.nnmode == 2) return;               // bracket already accepted
-    // bracket mode: searches are capped at hi^2 and stop at the first
+    // bracket mode (1): searches are capped at hi^2 and stop at the first
     // neighbour within lo^2; the output encodes 0 = within lo, the exact d^2
-    // in (lo^2, hi^2], +inf = nothing within hi
+    // in (lo^2, hi^2], +inf = nothing within hi.
+    // Refinement after a rejected bracket: the k-th smallest d^2 lies below
+    // lo^2 (mode 3: only queries coded 0 are searched, capped just above
+    // lo^2) or above hi^2 (mode 4: only queries coded +inf, uncapped); every
+    // other stored value already orders correctly against it.
     const bool brk = P.nnmode == 1;
-    const float cap = brk ? __uint_as_float(__float_as_uint(P.hi2) + 1u) : __builtin_huge_valf();
+    const float cap = brk ? __uint_as_float(__float_as_uint(P.hi2) + 1u)
+                    : P.nnmode == 3 ? __uint_as_float(__float_as_uint(P.lo2) + 1u)
+                                    : __builtin_huge_valf();
     const float lo2 = brk ? P.lo2 : -1.0f;
+    const float redo = P.nnmode == 3 ? 0.0f : __builtin_huge_valf();
+    const bool refine = P.nnmode >= 3;
     const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
     for (int64_t qm = ts; qm < te; qm++) {
+        if (refine && !(d2out[qm] == redo)) continue;
         const TQuery q = tq_load(T, qm, P, A.pp);
         const int32_t e0 = tb.leaf_of[qm];
         const int32_t* r0 = reinterpret_cast<const int32_t*>(tb.erec + 16 * (int64_t)e0);
