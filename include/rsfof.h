@@ -183,6 +183,23 @@ int rs_mlp_infer(const float* model, int64_t n, const float* features, float* ou
 int rs_profile_enable(int on);
 int rs_profile_get(const char* name, double* total_ms, int64_t* launches, double* units);
 
+/*
+ * Stable key/value sort, the primitive behind the cell-sorted layout of the
+ * 3D pass and the per-node member orders of the 6D pass (the per-process
+ * steps of the Parallelization section).  Sorts (keys_in[i], vals_in[i]) by
+ * the low `bits` bits of the key, ascending; equal keys keep their input
+ * order.  Bits above `bits` are carried but ignored for ordering.
+ *   keys_in, vals_in    device [n], only read
+ *   keys_out, vals_out  device [n], caller-allocated; must not alias the inputs
+ *   n                   0 <= n < 2^31
+ *   bits                1..64
+ * Stream-ordered (no host synchronisation).  Uses the library's workspace.
+ * Returns RS_OK, RS_EINVAL, RS_ENOMEM or RS_EDEVICE.
+ */
+int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out,
+                          const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits,
+                          void* stream);
+
 /* Releases an rs_tree* (struct and device arrays).  NULL is a no-op. */
 void rs_free(void* p);
 

@@ -23,7 +23,8 @@ RS_MLP_NPARAM = 5825
 
 EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
-            "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer")
+            "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
+            "rs_sort_pairs_u64_i32")
 
 
 class RsError(RuntimeError):
@@ -77,8 +78,9 @@ def load():
     lib.rs_mlp_train_step.argtypes = [P, P, P, i64, P, P, i64, f32, P, P]
     lib.rs_mlp_standardize.argtypes = [P, i64, P, P, ctypes.c_int, P]
     lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
+    lib.rs_sort_pairs_u64_i32.argtypes = [P, P, P, P, i64, ctypes.c_int, P]
     for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
-               "rs_mlp_infer"):
+               "rs_mlp_infer", "rs_sort_pairs_u64_i32"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -123,6 +125,20 @@ def rs_fof3d(x, y, z, box, link_len, labels=None, stream=None):
     if rc != RS_OK:
         raise RsError(rc, "rs_fof3d")
     return labels, int(ng.value)
+
+
+def rs_sort_pairs(keys, vals, bits=64, stream=None):
+    """Stable sort of (keys uint64 as int64 storage, vals int32) by the low
+    `bits` bits of the key; returns new (keys, vals) device tensors."""
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("vals size differs from keys")
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals)
+    _ck(load().rs_sort_pairs_u64_i32(_dev(keys, torch.int64, "keys"), _dev(ko, torch.int64, "keys"),
+                                     _dev(vals, torch.int32, "vals"), _dev(vo, torch.int32, "vals"),
+                                     n, int(bits), _stream(stream)), "rs_sort_pairs_u64_i32")
+    return ko, vo
 
 
 class _DevArray:

@@ -59,6 +59,24 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
                          model, out, static_cast<hipStream_t>(stream));
 }
 
+int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int32_t* vals_in,
+                          int32_t* vals_out, int64_t n, int bits, void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31 || bits < 1 || bits > 64) return RS_EINVAL;
+    if (n > 0 && (!keys_in || !keys_out || !vals_in || !vals_out)) return RS_EINVAL;
+    if (n > 0 && ((const void*)keys_in == (const void*)keys_out ||
+                  (const void*)vals_in == (const void*)vals_out))
+        return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    if (n == 0) return RS_OK;
+    rs::Arena* ar = nullptr;
+    const size_t tb = rs::sort_temp_bytes(n);
+    RS_TRY(rs::arena_reserve(4, tb, &ar));
+    void* temp = rs::arena_take(ar, tb);
+    if (!temp) return RS_EINTERNAL;
+    return rs::sort_pairs_u64_i32(keys_in, keys_out, vals_in, vals_out, n, bits, temp, tb,
+                                  static_cast<hipStream_t>(stream));
+}
+
 void rs_free(void* p) {
     if (!p) return;
     rs::tree_release(static_cast<rs_tree*>(p));

@@ -167,7 +167,8 @@ inline int hip_status(hipError_t e) {
 
 // Grow-only per-device workspaces with a bump allocator.  A call reserves
 // the footprint of one phase once, then carves sub-buffers (256-byte
-// aligned).  Index 0 serves the 3D pass, 1 and 2 the 6D pass.
+// aligned).  Index 0 serves the 3D pass, 1 and 2 the 6D pass, 3 the
+// proposer network, 4 the standalone sort.
 struct Arena {
     char* base = nullptr;
     size_t cap = 0;

@@ -2,7 +2,6 @@
 // fills, and the per-device workspace.
 #include "common.h"
 
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include <map>
 #include <mutex>
@@ -15,7 +14,7 @@ namespace rs {
 // workspace
 // ---------------------------------------------------------------------------
 
-static Arena g_arena[64][4];
+static Arena g_arena[64][5];
 static void* g_host_scratch[64];
 static size_t g_host_scratch_bytes[64];
 
@@ -24,7 +23,7 @@ size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 int arena_reserve(int which, size_t bytes, Arena** out) {
     int dev = 0;
     RS_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64 || which < 0 || which >= 4) return RS_EDEVICE;
+    if (dev < 0 || dev >= 64 || which < 0 || which >= 5) return RS_EDEVICE;
     Arena* a = &g_arena[dev][which];
     if (a->cap < bytes) {
         if (a->base) {
@@ -241,29 +240,6 @@ int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* temp,
     RS_TRY(scan_exclusive_i32(sums, sums, nb, rest, total_dev, st));
     k_tile_scan<<<(unsigned)nb, SCAN_BT, 0, st>>>(in, out, sums, n, nullptr);
     RS_HIP(hipGetLastError());
-    return RS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// key/value sort (LSD radix over the low `bits` bits of the key)
-// ---------------------------------------------------------------------------
-
-size_t sort_temp_bytes(int64_t n) {
-    size_t bytes = 0;
-    rocprim::radix_sort_pairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                              (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)n, 0, 64);
-    return arena_round(bytes);
-}
-
-int sort_pairs_u64_i32(const uint64_t* kin, uint64_t* kout, const int32_t* vin,
-                       int32_t* vout, int64_t n, int bits, void* temp, size_t temp_bytes,
-                       hipStream_t st) {
-    if (n <= 0) return RS_OK;
-    if (bits < 1) bits = 1;
-    if (bits > 64) bits = 64;
-    size_t tb = temp_bytes;
-    RS_HIP(rocprim::radix_sort_pairs(temp, tb, kin, kout, vin, vout, (size_t)n, 0u,
-                                     (unsigned)bits, st));
     return RS_OK;
 }
 

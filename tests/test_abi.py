@@ -83,3 +83,14 @@ def test_phase_rejects_bad_arguments_before_device_work(kw):
 def test_no_device_reports_edevice():
     rc, ng = _fof3d_raw(10, 10.0, 0.2)
     assert rc == rs.RS_EDEVICE and ng == 7
+
+
+@pytest.mark.parametrize("n,bits,alias", [(-1, 8, False), (1 << 31, 8, False), (4, 0, False),
+                                          (4, 65, False), (4, 8, True)])
+def test_sort_rejects_bad_arguments(n, bits, alias):
+    lib = rs.load()
+    a = ctypes.c_void_p(0x1000)
+    b = a if alias else ctypes.c_void_p(0x2000)
+    rc = lib.rs_sort_pairs_u64_i32(a, b, ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), n,
+                                   bits, None)
+    assert rc == rs.RS_EINVAL
