@@ -218,6 +218,7 @@ def main():
     model = learn.load_model()
     dev = torch.device("cuda:0")
     arrs = synth.generate(cfg, 0, device=dev)
+    torch.cuda.empty_cache()           # the generator's fp64 temporaries
     labels = torch.empty(cfg.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 

@@ -200,6 +200,16 @@ int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out,
                           const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits,
                           void* stream);
 
+/*
+ * Releases the library's device workspaces on the current device.  The
+ * library keeps grow-only workspaces between calls so repeated calls do not
+ * allocate; a caller that needs the memory back (for example before working
+ * on a 1024^3 result itself) calls this.  The next call allocates again.
+ * Must not overlap a running library call on the same device.  Returns RS_OK
+ * or RS_EDEVICE.
+ */
+int rs_release_workspace(void);
+
 /* Releases an rs_tree* (struct and device arrays).  NULL is a no-op. */
 void rs_free(void* p);
 

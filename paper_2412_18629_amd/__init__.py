@@ -24,7 +24,7 @@ RS_MLP_NPARAM = 5825
 EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
             "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
-            "rs_sort_pairs_u64_i32")
+            "rs_sort_pairs_u64_i32", "rs_release_workspace")
 
 
 class RsError(RuntimeError):
@@ -79,8 +79,9 @@ def load():
     lib.rs_mlp_standardize.argtypes = [P, i64, P, P, ctypes.c_int, P]
     lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
     lib.rs_sort_pairs_u64_i32.argtypes = [P, P, P, P, i64, ctypes.c_int, P]
+    lib.rs_release_workspace.argtypes = []
     for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
-               "rs_mlp_infer", "rs_sort_pairs_u64_i32"):
+               "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -139,6 +140,11 @@ def rs_sort_pairs(keys, vals, bits=64, stream=None):
                                      _dev(vals, torch.int32, "vals"), _dev(vo, torch.int32, "vals"),
                                      n, int(bits), _stream(stream)), "rs_sort_pairs_u64_i32")
     return ko, vo
+
+
+def rs_release_workspace():
+    """Give the library's device workspaces back (the next call reallocates)."""
+    _ck(load().rs_release_workspace(), "rs_release_workspace")
 
 
 class _DevArray:

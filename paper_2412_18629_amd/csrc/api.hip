@@ -38,6 +38,7 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float bo
         if (n_groups) *n_groups = 0;
         return RS_OK;
     }
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_3D));
     return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
                          static_cast<hipStream_t>(stream));
 }
@@ -55,6 +56,8 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
     if ((flags & 0xffu) == RS_LEARNED && !model) return RS_EINVAL;
     if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !fof_labels)) return RS_EINVAL;
     RS_TRY(rs::device_ready());
+    RS_TRY(rs::arena_call_begin((1u << rs::AR_PHASE) | (1u << rs::AR_LARGE) |
+                                (1u << rs::AR_TREE) | (1u << rs::AR_MLP)));
     return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,
                          model, out, static_cast<hipStream_t>(stream));
 }
@@ -70,11 +73,19 @@ int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int
     if (n == 0) return RS_OK;
     rs::Arena* ar = nullptr;
     const size_t tb = rs::sort_temp_bytes(n);
-    RS_TRY(rs::arena_reserve(4, tb, &ar));
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_SORT));
+    RS_TRY(rs::arena_reserve(rs::AR_SORT, tb, &ar));
     void* temp = rs::arena_take(ar, tb);
     if (!temp) return RS_EINTERNAL;
     return rs::sort_pairs_u64_i32(keys_in, keys_out, vals_in, vals_out, n, bits, temp, tb,
                                   static_cast<hipStream_t>(stream));
+}
+
+int rs_release_workspace(void) {
+    RS_TRY(rs::device_ready());
+    RS_HIP(hipDeviceSynchronize());
+    for (int k = 0; k < rs::N_ARENAS; k++) RS_TRY(rs::arena_release(k));
+    return RS_OK;
 }
 
 void rs_free(void* p) {

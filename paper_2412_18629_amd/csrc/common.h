@@ -167,14 +167,24 @@ inline int hip_status(hipError_t e) {
 
 // Grow-only per-device workspaces with a bump allocator.  A call reserves
 // the footprint of one phase once, then carves sub-buffers (256-byte
-// aligned).  Index 0 serves the 3D pass, 1 and 2 the 6D pass, 3 the
-// proposer network, 4 the standalone sort.
+// aligned).  Indices: AR_3D, AR_PHASE / AR_LARGE / AR_TREE (6D pass), AR_MLP
+// (proposer network), AR_SORT (standalone sort).
 struct Arena {
     char* base = nullptr;
     size_t cap = 0;
     size_t off = 0;
 };
 
+constexpr int N_ARENAS = 6;
+constexpr int AR_3D = 0, AR_PHASE = 1, AR_LARGE = 2, AR_MLP = 3, AR_SORT = 4, AR_TREE = 5;
+// The arenas an API call uses; when a reservation cannot be met, the
+// device's other arenas (left by earlier calls of other phases) are
+// released and the allocation is tried again.
+int arena_call_begin(uint32_t keep_mask);
+// device bytes the current call could obtain: free memory plus the arenas it
+// does not hold plus those in replace_mask (about to be re-reserved)
+int device_budget(uint32_t replace_mask, size_t* bytes);
+int arena_release(int which);
 int arena_reserve(int which, size_t bytes, Arena** out);   // resets the bump pointer
 void* arena_take(Arena* a, size_t bytes);       // NULL if the reservation is exceeded
 size_t arena_round(size_t bytes);

@@ -221,7 +221,8 @@ static int mlp_scratch(int64_t n, float** h1, float** h2, float** y, float** dy,
     add(4 * NH * n); add(4 * NH * n); add(4 * n); add(4 * n); add(4 * NH * n); add(4 * NH * n);
     add(4 * NPARAM); add(64);
     Arena* ar;
-    RS_TRY(arena_reserve(3, b, &ar));
+    RS_TRY(arena_call_begin(1u << AR_MLP));   // only the standalone proposer entry points get here
+    RS_TRY(arena_reserve(AR_MLP, b, &ar));
     *h1 = take<float>(ar, NH * n);
     *h2 = take<float>(ar, NH * n);
     *y = take<float>(ar, n);

@@ -206,7 +206,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     for (int k = 0; k < 9; k++) add(4 * (size_t)cap);         // records
     add(8 * (size_t)cap); add(8 * (size_t)cap); add(4 * (size_t)cap); add(4 * (size_t)cap);
     add(4 * (size_t)cap);                                      // canon
-    add(sizeof(SmallItem) * 4 * (size_t)(n / 2 + 2));          // level-0 buckets
+    const int64_t bstride = n / (min_group > 1 ? min_group : 1) + 2;   // groups per bucket, at most
+    add(sizeof(SmallItem) * 4 * (size_t)bstride);              // level-0 buckets
     add(sizeof(ChildOut) * (size_t)(n / (SMALL_MAX + 1) + 2));
     add(sort_temp_bytes(cap > n ? cap : n)); add(scan_temp_bytes(n)); add(256);
     const bool want_feat = pp.want_feat != 0;
@@ -214,7 +215,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     const size_t model_floats = 2 * RS_NFEAT + RS_MLP_NPARAM;
     add(4 * model_floats);
     Arena* ar;
-    RS_TRY(arena_reserve(1, bytes, &ar));
+    RS_TRY(arena_reserve(AR_PHASE, bytes, &ar));
     uint64_t* lkin = take<uint64_t>(ar, n);
     uint64_t* lkout = take<uint64_t>(ar, n);
     int32_t* lvin = take<int32_t>(ar, n);
@@ -249,7 +250,6 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     int32_t* ovin = take<int32_t>(ar, cap);
     int32_t* order = take<int32_t>(ar, cap);
     int32_t* canon = take<int32_t>(ar, cap);
-    const int64_t bstride = n / 2 + 2;
     SmallItem* buckets = take<SmallItem>(ar, 4 * bstride);
     ChildOut* large0 = take<ChildOut>(ar, n / (SMALL_MAX + 1) + 2);
     size_t stb = sort_temp_bytes(cap > n ? cap : n);
@@ -311,16 +311,39 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         std::sort(large.begin(), large.end(),
                   [](const ChildOut& a, const ChildOut& b) { return a.slot < b.slot; });
     }
-    int64_t mlarge = 0;
-    for (auto& c : large) mlarge += c.size;
+    int64_t mlarge = 0, mmax = 0;
+    for (auto& c : large) {
+        mlarge += c.size;
+        mmax = c.size > mmax ? c.size : mmax;
+    }
 
     // ---- large-node work space (arena 2) ----
+    // Members one pass of the level pipeline holds: every large group at once
+    // when the device has room, else consecutive chunks of groups (each group
+    // whole), sized from the memory this call can obtain.  The plain form
+    // walks one group at a time and needs room for the largest only.
+    int64_t mcap = form == RS_PLAIN ? mmax : mlarge;
+    if (mcap > mmax) {
+        size_t budget = 0;
+        RS_TRY(device_budget((1u << AR_LARGE) | (1u << AR_TREE), &budget));
+        const int64_t probe = (int64_t)1 << 24;
+        const double per = (double)large_work_bytes(probe, pp.min_sub) / (double)probe + 16.0;
+        const size_t keep = (size_t)cap * (9 * 4 + 4 * (want_feat ? RS_NFEAT : 0)) +
+                            (size_t)n * 4 + ((size_t)2 << 30);
+        const int64_t fit = budget > keep ? (int64_t)((double)(budget - keep) / per) : 0;
+        if (fit < mcap) mcap = fit > mmax ? fit : mmax;
+        // test hook: a smaller chunk budget exercises the chunked path on small inputs
+        if (const char* e = getenv("RS_DEBUG_CHUNK_MEMBERS")) {
+            const int64_t v = atoll(e);
+            if (v > 0 && v < mcap) mcap = v > mmax ? v : mmax;
+        }
+    }
     LargeWork lw;
     int64_t n_acc = 0, n_fb = 0;
     if (nlarge > 0) {
         Arena* ar2;
-        RS_TRY(arena_reserve(2, large_work_bytes(mlarge), &ar2));
-        RS_TRY(large_work_carve(ar2, mlarge, &lw));
+        RS_TRY(arena_reserve(AR_LARGE, large_work_bytes(mcap, pp.min_sub), &ar2));
+        RS_TRY(large_work_carve(ar2, mcap, pp.min_sub, &lw));
         if (form == RS_LEARNED) {
             RS_HIP(hipMemcpyAsync(model_dev, model_host, 4 * model_floats, hipMemcpyHostToDevice,
                                   st));
@@ -359,7 +382,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
                     RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc,
                                        &n_fb, st));
                     cur.swap(nxt);
-                    in = &lw.N;
+                    in = &lw.SN;
                 }
                 li++;
             }
@@ -367,13 +390,21 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     } else {
         for (int b = 3; b >= 0; b--)
             RS_TRY(run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, st));
-        std::vector<ChildOut> cur = large, nxt;
-        const Members* in = &A;
-        while (!cur.empty()) {
-            RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc, &n_fb,
-                               st));
-            cur.swap(nxt);
-            in = &lw.N;
+        size_t li = 0;
+        while (li < large.size()) {
+            std::vector<ChildOut> cur, nxt;
+            int64_t sum = 0;
+            while (li < large.size() && (cur.empty() || sum + large[li].size <= mcap)) {
+                sum += large[li].size;
+                cur.push_back(large[li++]);
+            }
+            const Members* in = &A;
+            while (!cur.empty()) {
+                RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc,
+                                   &n_fb, st));
+                cur.swap(nxt);
+                in = &lw.SN;
+            }
         }
     }
 
@@ -401,9 +432,14 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     char* blk = nullptr;
     hipError_t e = hipMalloc((void**)&blk, total);
     if (e != hipSuccess) {
+        // the level work spaces are done with; give them back and try again
         (void)hipGetLastError();
-        free(t);
-        return RS_ENOMEM;
+        if (arena_release(AR_LARGE) != RS_OK || arena_release(AR_TREE) != RS_OK ||
+            hipMalloc((void**)&blk, total) != hipSuccess) {
+            (void)hipGetLastError();
+            free(t);
+            return RS_ENOMEM;
+        }
     }
     t->n_nodes = m;
     t->n_particles = n;

@@ -124,7 +124,8 @@ constexpr int64_t O32_LIMIT = (int64_t)1 << 30;
 
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,
-               const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st);
+               const PhaseParams& pp, std::vector<int32_t>* level_begin, bool* overflow,
+               hipStream_t st);
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Blocks are remapped so that every XCD runs consecutive chunks of C
 // tiles: neighbouring tiles, which read mostly the same candidate data, then
@@ -154,7 +155,8 @@ int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStre
 // large-node members (which bounds every later level)
 struct LargeWork {
     int64_t cap_m, cap_nodes, cap_items, cap_tiles, cap_supers, cap_small;
-    Members T, S, N;
+    Members T;           // this level's members in 6D Morton order
+    Members SN;          // children: small ones from the front, large ones from the back
     uint64_t *kin, *kout;
     int32_t *src, *perm, *mnode, *par, *cnt, *cslot, *cfill;
     int64_t* coff;
@@ -186,8 +188,11 @@ struct LargeWork {
     const float* model;  // device copy of the proposer, or NULL (exact search)
 };
 
-size_t large_work_bytes(int64_t m);
-int large_work_carve(Arena* ar, int64_t m, LargeWork* w);
+size_t large_work_bytes(int64_t m, int32_t min_sub);
+int large_work_carve(Arena* ar, int64_t m, int32_t min_sub, LargeWork* w);
+// (re)reserves the search-tree buffers for up to m members and nv nodes;
+// grow > 1 multiplies the entry and internal-node capacities
+int tree_reserve(LargeWork* w, int64_t m, int64_t nv, int64_t grow);
 int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Members& mb,
                        const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
                        hipStream_t st);

@@ -23,6 +23,8 @@
 // metric); nodes spanning more than a quarter box per axis are not culled.
 #include "phase_common.h"
 
+#include <stdlib.h>
+
 namespace rs {
 
 
@@ -419,7 +421,8 @@ __global__ void k_lchild(int64_t m, const int32_t* __restrict__ par,
                          PhaseParams pp, NodeRec nr, int32_t* __restrict__ cslot,
                          int64_t* __restrict__ coff, int32_t* __restrict__ cfill,
                          int8_t* __restrict__ cclass, LCounters* __restrict__ ctr,
-                         SmallItem* __restrict__ small_items, ChildOut* __restrict__ large_out) {
+                         SmallItem* __restrict__ small_items, ChildOut* __restrict__ large_out,
+                         int64_t cap_m) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= m) return;
     if (par[t] != (int32_t)t) return;
@@ -444,7 +447,8 @@ __global__ void k_lchild(int64_t m, const int32_t* __restrict__ par,
         small_items[i] = SmallItem{slot, nd.level + 1, c, minidx, off};
         cclass[t] = 0;
     } else {
-        off = (int64_t)atomicAdd(&ctr->tot_large, (unsigned long long)c);
+        // large children fill the shared child buffer from its end
+        off = cap_m - (int64_t)atomicAdd(&ctr->tot_large, (unsigned long long)c) - c;
         int i = atomicAdd(&ctr->n_large, 1);
         large_out[i] = ChildOut{slot, c, minidx, nd.level + 1, off};
         cclass[t] = 1;
@@ -602,15 +606,18 @@ __global__ void k_bucket(const SmallItem* __restrict__ in, int n, SmallItem* __r
 // host side of one level
 // ---------------------------------------------------------------------------
 
-size_t large_work_bytes(int64_t m) {
+// Bytes of the large-node work space for up to m members per pass.  Small
+// children hold at least min_sub members each and are disjoint, so at most
+// m / min_sub of them exist per level.
+size_t large_work_bytes(int64_t m, int32_t min_sub) {
     int64_t nodes = m / (SMALL_MAX + 1) + 2;
     int64_t items = m / 4096 + nodes + 2;
     int64_t tiles = m / 64 + nodes + 2;
     int64_t supers = tiles / 64 + nodes + 2;
-    int64_t small = m / 2 + 2;
+    int64_t small = m / (min_sub > 1 ? min_sub : 1) + 2;
     size_t b = 0;
     auto add = [&](size_t x) { b += arena_round(x); };
-    for (int k = 0; k < 3 * 7; k++) add(4 * m);                 // T, S, N
+    for (int k = 0; k < 2 * 7; k++) add(4 * m);                 // T, SN
     add(8 * m); add(8 * m);                                     // keys
     for (int k = 0; k < 7; k++) add(4 * m);                     // src..cfill
     add(8 * m); add(m); add(8 * m); add(4 * m);                 // coff, cclass, mpk, d2
@@ -620,22 +627,19 @@ size_t large_work_bytes(int64_t m) {
     add(sizeof(LCounters)); add(sizeof(SmallItem) * small); add(sizeof(SmallItem) * 4 * small);
     add(64); add(sizeof(ChildOut) * nodes);
     add(sort_temp_bytes(m));
-    int64_t cap_inode = m / 8 + nodes + 64, cap_entry = m + m / 8 + nodes + 64;
-    for (int k = 0; k < 5; k++) add(4 * cap_inode);            // tree internal nodes
-    for (int k = 0; k < 3; k++) add(4 * cap_entry);            // tree entries
-    add(4 * 16 * cap_entry); add(4 * m); add(64); add(4 * nodes);
-    add(4 * 16 * nodes); add(4 * RS_NFEAT * nodes); add(4 * nodes); add(4 * 2 * nodes); add(64);
+    add(4 * nodes); add(4 * 16 * nodes); add(4 * RS_NFEAT * nodes); add(4 * nodes);
+    add(4 * 2 * nodes); add(64);
     return b + 4096;
 }
 
-int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
+int large_work_carve(Arena* ar, int64_t m, int32_t min_sub, LargeWork* w) {
     w->cap_m = m;
     w->cap_nodes = m / (SMALL_MAX + 1) + 2;
     w->cap_items = m / 4096 + w->cap_nodes + 2;
     w->cap_tiles = m / 64 + w->cap_nodes + 2;
     w->cap_supers = w->cap_tiles / 64 + w->cap_nodes + 2;
-    w->cap_small = m / 2 + 2;
-    Members* bufs[3] = {&w->T, &w->S, &w->N};
+    w->cap_small = m / (min_sub > 1 ? min_sub : 1) + 2;
+    Members* bufs[2] = {&w->T, &w->SN};
     for (Members* b : bufs) {
         b->x = take<float>(ar, m); b->y = take<float>(ar, m); b->z = take<float>(ar, m);
         b->vx = take<float>(ar, m); b->vy = take<float>(ar, m); b->vz = take<float>(ar, m);
@@ -671,8 +675,37 @@ int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
     w->large_out = take<ChildOut>(ar, w->cap_nodes);
     w->sort_temp_bytes = sort_temp_bytes(m);
     w->sort_temp = arena_take(ar, w->sort_temp_bytes);
-    const int64_t cap_inode = m / 8 + w->cap_nodes + 64;
-    const int64_t cap_entry = m + m / 8 + w->cap_nodes + 64;
+    w->root = take<int32_t>(ar, w->cap_nodes);
+    w->lhist = take<int32_t>(ar, 16 * w->cap_nodes);
+    w->lfeat = take<float>(ar, RS_NFEAT * w->cap_nodes);
+    w->lnl = take<float>(ar, w->cap_nodes);
+    w->lcnt = take<int32_t>(ar, 2 * w->cap_nodes);
+    w->lstat = take<int32_t>(ar, 16);
+    w->model = nullptr;
+    w->tb.cap_entry = 0;
+    return (w->sort_temp && w->lstat) ? RS_OK : RS_EINTERNAL;
+}
+
+// Entries: one per child cell record and per leaf (leaves hold up to 64
+// members, about 50 on average); the estimate below is several times the
+// usual count and grows on overflow.
+int tree_reserve(LargeWork* w, int64_t m, int64_t nv, int64_t grow) {
+    int64_t cap_inode = (m / 64 + 2 * nv + 1024) * grow;
+    int64_t cap_entry = (m / 12 + 64 * nv + 4096) * grow;
+    // test hook: a small first capacity exercises the overflow and rebuild path
+    if (const char* e = getenv("RS_DEBUG_TREE_ENTRIES")) {
+        const int64_t v = atoll(e) * grow;
+        if (v > 0 && v < cap_entry) cap_entry = v;
+    }
+    if (cap_inode > 0x7fffffffll) cap_inode = 0x7fffffffll;
+    if (cap_entry > 0x7fffffffll) cap_entry = 0x7fffffffll;
+    size_t b = 0;
+    auto add = [&](size_t x) { b += arena_round(x); };
+    for (int k = 0; k < 5; k++) add(4 * cap_inode);
+    for (int k = 0; k < 3; k++) add(4 * cap_entry);
+    add(4 * 16 * cap_entry); add(4 * m); add(64);
+    Arena* ar;
+    RS_TRY(arena_reserve(AR_TREE, b + 4096, &ar));
     TreeBuf& tb = w->tb;
     tb.istart = take<int32_t>(ar, cap_inode);
     tb.iend = take<int32_t>(ar, cap_inode);
@@ -685,19 +718,13 @@ int large_work_carve(Arena* ar, int64_t m, LargeWork* w) {
     tb.erec = take<float>(ar, 16 * cap_entry);
     tb.leaf_of = take<int32_t>(ar, m);
     int32_t* ctr = take<int32_t>(ar, 16);
+    if (!ctr) return RS_EINTERNAL;
     tb.n_inode = ctr;
     tb.n_entry = ctr + 1;
     tb.overflow = ctr + 2;
     tb.cap_inode = (int32_t)cap_inode;
     tb.cap_entry = (int32_t)cap_entry;
-    w->root = take<int32_t>(ar, w->cap_nodes);
-    w->lhist = take<int32_t>(ar, 16 * w->cap_nodes);
-    w->lfeat = take<float>(ar, RS_NFEAT * w->cap_nodes);
-    w->lnl = take<float>(ar, w->cap_nodes);
-    w->lcnt = take<int32_t>(ar, 2 * w->cap_nodes);
-    w->lstat = take<int32_t>(ar, 16);
-    w->model = nullptr;
-    return (w->sort_temp && w->lstat) ? RS_OK : RS_EINTERNAL;
+    return RS_OK;
 }
 
 // Launches the small-subtree kernels over a device list of small items whose
@@ -721,7 +748,7 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
 }
 
 // One level over the large nodes `hn` (host copies) whose members live in
-// `in`.  Appends the next level's large nodes to `next` (offsets into w->N).
+// `in`.  Appends the next level's large nodes to `next` (offsets into w->SN).
 int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
                 const float* X, const float* Y, const float* Z, const PhaseParams& pp,
                 const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
@@ -784,8 +811,16 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     k_lcull<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->sbox, pp, w->prm);
     RS_HIP(hipGetLastError());
     std::vector<int32_t> tree_levels;
-    RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
-                      &tree_levels, st));
+    // search tree; its buffers grow and the build is redone on overflow
+    if (w->tb.cap_entry == 0) RS_TRY(tree_reserve(w, w->cap_m, w->cap_nodes, 1));
+    for (int64_t grow = 2;; grow *= 2) {
+        bool tree_overflow = false;
+        RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
+                          &tree_levels, &tree_overflow, st));
+        if (!tree_overflow) break;
+        if (grow > 1024) return RS_EINTERNAL;
+        RS_TRY(tree_reserve(w, w->cap_m, w->cap_nodes, grow));
+    }
     TArgs TA{w->mnode, w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
              8.0f * pp.L * 5.9604645e-08f, M};
     // proposer features (when requested or when a proposal is wanted)
@@ -840,14 +875,14 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     RS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(LCounters), st));
     k_lchild<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk, w->mnode, w->nodes, pp, nr, w->cslot,
                                 w->coff, w->cfill, w->cclass, w->ctr, w->small_items,
-                                w->large_out);
-    k_lscatter<<<gm, BT, 0, st>>>(M, w->par, w->T, w->cslot, w->coff, w->cfill, w->cclass, w->S,
-                                  w->N, deepest);
+                                w->large_out, w->cap_m);
+    k_lscatter<<<gm, BT, 0, st>>>(M, w->par, w->T, w->cslot, w->coff, w->cfill, w->cclass, w->SN,
+                                  w->SN, deepest);
     RS_HIP(hipGetLastError());
     LCounters hc;
     RS_HIP(hipMemcpyAsync(&hc, w->ctr, sizeof(LCounters), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
-    RS_TRY(launch_small_items(w, w->small_items, hc.n_small, w->S, nr, pp, deepest, st));
+    RS_TRY(launch_small_items(w, w->small_items, hc.n_small, w->SN, nr, pp, deepest, st));
     next->resize(hc.n_large);
     if (hc.n_large > 0) {
         RS_HIP(hipMemcpyAsync(next->data(), w->large_out, sizeof(ChildOut) * hc.n_large,

@@ -462,7 +462,9 @@ __global__ void k_tree_roots(int nv, const LNode* __restrict__ nodes, TreeBuf tb
 
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,
-               const PhaseParams& pp, std::vector<int32_t>* level_begin, hipStream_t st) {
+               const PhaseParams& pp, std::vector<int32_t>* level_begin, bool* overflow,
+               hipStream_t st) {
+    *overflow = false;
     int32_t* hc = nullptr;
     RS_TRY(host_scratch((void**)&hc, 64));
     RS_HIP(hipMemsetAsync(tb.n_entry, 0, sizeof(int32_t), st));
@@ -481,7 +483,10 @@ int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* n
         RS_HIP(hipMemcpyAsync(hc, tb.n_inode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         RS_HIP(hipMemcpyAsync(hc + 1, tb.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         RS_HIP(hipStreamSynchronize(st));
-        if (hc[1]) return RS_EINTERNAL;
+        if (hc[1]) {
+            *overflow = true;
+            return RS_OK;
+        }
         b = e;
         e = hc[0];
         if (e == b) break;

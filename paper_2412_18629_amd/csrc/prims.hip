@@ -14,16 +14,67 @@ namespace rs {
 // workspace
 // ---------------------------------------------------------------------------
 
-static Arena g_arena[64][5];
+static Arena g_arena[64][N_ARENAS];
+static uint32_t g_keep[64];          // arenas the current call holds (never released)
 static void* g_host_scratch[64];
 static size_t g_host_scratch_bytes[64];
 
 size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 
+static int current_device(int* dev) {
+    RS_HIP(hipGetDevice(dev));
+    return (*dev < 0 || *dev >= 64) ? RS_EDEVICE : RS_OK;
+}
+
+int arena_call_begin(uint32_t keep_mask) {
+    int dev = 0;
+    RS_TRY(current_device(&dev));
+    g_keep[dev] = keep_mask;
+    return RS_OK;
+}
+
+// releases the device's arenas that the current call does not hold
+static int arena_release_idle(int dev) {
+    for (int k = 0; k < N_ARENAS; k++) {
+        Arena* a = &g_arena[dev][k];
+        if ((g_keep[dev] >> k) & 1u) continue;
+        if (a->base) {
+            RS_HIP(hipFree(a->base));
+            a->base = nullptr;
+            a->cap = 0;
+        }
+    }
+    return RS_OK;
+}
+
+int device_budget(uint32_t replace_mask, size_t* bytes) {
+    int dev = 0;
+    RS_TRY(current_device(&dev));
+    size_t fr = 0, tot = 0;
+    RS_HIP(hipMemGetInfo(&fr, &tot));
+    for (int k = 0; k < N_ARENAS; k++)
+        if (!((g_keep[dev] >> k) & 1u) || ((replace_mask >> k) & 1u)) fr += g_arena[dev][k].cap;
+    *bytes = fr;
+    return RS_OK;
+}
+
+int arena_release(int which) {
+    int dev = 0;
+    RS_TRY(current_device(&dev));
+    if (which < 0 || which >= N_ARENAS) return RS_EDEVICE;
+    Arena* a = &g_arena[dev][which];
+    if (a->base) {
+        RS_HIP(hipFree(a->base));
+        a->base = nullptr;
+        a->cap = 0;
+    }
+    return RS_OK;
+}
+
 int arena_reserve(int which, size_t bytes, Arena** out) {
     int dev = 0;
-    RS_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64 || which < 0 || which >= 5) return RS_EDEVICE;
+    RS_TRY(current_device(&dev));
+    if (which < 0 || which >= N_ARENAS) return RS_EDEVICE;
     Arena* a = &g_arena[dev][which];
     if (a->cap < bytes) {
         if (a->base) {
@@ -31,12 +82,19 @@ int arena_reserve(int which, size_t bytes, Arena** out) {
             a->base = nullptr;
             a->cap = 0;
         }
-        size_t want = arena_round(bytes + bytes / 8 + (1 << 20));
+        size_t slack = bytes / 16 < ((size_t)1 << 30) ? bytes / 16 : ((size_t)1 << 30);
+        size_t want = arena_round(bytes + slack + (1 << 20));
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, want);
         if (e != hipSuccess) {
+            // give back what other phases left behind, then try again
             (void)hipGetLastError();
-            return RS_ENOMEM;
+            RS_TRY(arena_release_idle(dev));
+            e = hipMalloc(&p, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return RS_ENOMEM;
+            }
         }
         a->base = static_cast<char*>(p);
         a->cap = want;

@@ -198,6 +198,47 @@ def _integer_counts(own, total):
     return fl.to(torch.int64)
 
 
+# Boxes above this many particles draw their halo particles in chunks of
+# CHUNK particles (fp32 output written as it goes) so the fp64 intermediates
+# stay bounded; smaller boxes draw everything at once.  The draw order differs
+# between the two paths, so each is its own deterministic workload.
+CHUNKED_ABOVE = 1 << 28
+CHUNK = 1 << 25
+
+
+def _halo_particles_chunked(cfg, g, device, cat, counts, n_bg):
+    n_obj = counts.numel()
+    m = int(counts.sum().item())
+    conc_obj = _uniform(g, (n_obj,), cfg.conc[0], cfg.conc[1], device)
+    first = torch.cumsum(counts, 0) - counts          # first particle of each object
+    pos32 = torch.empty((cfg.n, 3), dtype=torch.float32, device=device)
+    vel32 = torch.empty((cfg.n, 3), dtype=torch.float32, device=device)
+    for p0 in range(0, m, CHUNK):
+        p1 = min(p0 + CHUNK, m)
+        ids = torch.arange(p0, p1, device=device)
+        obj = torch.searchsorted(first, ids, right=True) - 1
+        mass = cat["mass"][obj]
+        conc = conc_obj[obj]
+        rv = _rvir(mass, cfg)
+        x = _nfw_radius(_uniform(g, (p1 - p0,), 0.0, 1.0, device), conc)
+        r = x * (rv / conc)
+        pos = cat["centre"][obj] + _unit_vectors(g, p1 - p0, device) * r[:, None]
+        pos32[p0:p1] = torch.remainder(pos, cfg.box).to(torch.float32)
+        sig = _sigma1d(mass, cfg)
+        vel = cat["bulk"][obj] + torch.randn((p1 - p0, 3), generator=g, dtype=torch.float64,
+                                             device=device) * sig[:, None]
+        vel32[p0:p1] = vel.to(torch.float32)
+        del ids, obj, mass, conc, rv, x, r, pos, sig, vel
+    for b0 in range(0, n_bg, CHUNK):
+        b1 = min(b0 + CHUNK, n_bg)
+        bpos = _uniform(g, (b1 - b0, 3), 0.0, cfg.box, device)
+        pos32[m + b0:m + b1] = torch.remainder(bpos, cfg.box).to(torch.float32)
+        bvel = torch.randn((b1 - b0, 3), generator=g, dtype=torch.float64,
+                           device=device) * cfg.sigma_bg
+        vel32[m + b0:m + b1] = bvel.to(torch.float32)
+    return pos32, vel32, m
+
+
 def generate(cfg: SynthConfig | str, seed: int = 0, device="cpu", return_meta=False):
     """Generate (x, y, z, vx, vy, vz) as fp32 tensors on ``device``.
 
@@ -214,30 +255,34 @@ def generate(cfg: SynthConfig | str, seed: int = 0, device="cpu", return_meta=Fa
     counts = _integer_counts(cat["own"], n_halo_target)
     n_bg = cfg.n - n_halo_target
     n_obj = counts.numel()
-    obj = torch.repeat_interleave(torch.arange(n_obj, device=device), counts)
-    m = obj.numel()
-    mass = cat["mass"][obj]
-    conc = _uniform(g, (n_obj,), cfg.conc[0], cfg.conc[1], device)[obj]
-    rv = _rvir(mass, cfg)
-    x = _nfw_radius(_uniform(g, (m,), 0.0, 1.0, device), conc)
-    r = x * (rv / conc)
-    pos = cat["centre"][obj] + _unit_vectors(g, m, device) * r[:, None]
-    sig = _sigma1d(mass, cfg)
-    vel = cat["bulk"][obj] + torch.randn((m, 3), generator=g, dtype=torch.float64,
-                                         device=device) * sig[:, None]
-    del mass, conc, rv, x, r, sig
-    bpos = _uniform(g, (n_bg, 3), 0.0, cfg.box, device)
-    bvel = torch.randn((n_bg, 3), generator=g, dtype=torch.float64, device=device) * cfg.sigma_bg
-    pos = torch.cat([pos, bpos])
-    vel = torch.cat([vel, bvel])
-    del bpos, bvel
-    pos = torch.remainder(pos, cfg.box)
-    pos32 = pos.to(torch.float32)
-    del pos
+    if cfg.n > CHUNKED_ABOVE:
+        pos32, vel32, m = _halo_particles_chunked(cfg, g, device, cat, counts, n_bg)
+    else:
+        obj = torch.repeat_interleave(torch.arange(n_obj, device=device), counts)
+        m = obj.numel()
+        mass = cat["mass"][obj]
+        conc = _uniform(g, (n_obj,), cfg.conc[0], cfg.conc[1], device)[obj]
+        rv = _rvir(mass, cfg)
+        x = _nfw_radius(_uniform(g, (m,), 0.0, 1.0, device), conc)
+        r = x * (rv / conc)
+        pos = cat["centre"][obj] + _unit_vectors(g, m, device) * r[:, None]
+        sig = _sigma1d(mass, cfg)
+        vel = cat["bulk"][obj] + torch.randn((m, 3), generator=g, dtype=torch.float64,
+                                             device=device) * sig[:, None]
+        del mass, conc, rv, x, r, sig
+        bpos = _uniform(g, (n_bg, 3), 0.0, cfg.box, device)
+        bvel = torch.randn((n_bg, 3), generator=g, dtype=torch.float64,
+                           device=device) * cfg.sigma_bg
+        pos = torch.cat([pos, bpos])
+        vel = torch.cat([vel, bvel])
+        del bpos, bvel
+        pos = torch.remainder(pos, cfg.box)
+        pos32 = pos.to(torch.float32)
+        del pos
+        vel32 = vel.to(torch.float32)
+        del vel
     box32 = torch.tensor(cfg.box, dtype=torch.float32, device=device)
     pos32 = torch.where(pos32 >= box32, torch.zeros_like(pos32), pos32)
-    vel32 = vel.to(torch.float32)
-    del vel
     perm = torch.randperm(cfg.n, generator=g, device=device)
     pos32 = pos32[perm]
     vel32 = vel32[perm]

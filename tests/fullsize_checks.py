@@ -119,10 +119,11 @@ def stratified(sizes, groups, n_pick, min_group, seed=0):
     return groups[np.concatenate(pick)]
 
 
-def check_all(R, cfg, n_sample=64, subtree_max=150000, log=print):
+def check_all(R, cfg, n_sample=64, subtree_max=150000, closure_max=None, log=print):
     """Structural invariants of the whole tree, level-0 moments of every
-    group, 3D closure of sampled groups and 6D subtrees of sampled groups up
-    to subtree_max members.  Raises AssertionError on the first failure."""
+    group, 3D closure of sampled groups (up to closure_max members when
+    given) and 6D subtrees of sampled groups up to subtree_max members.
+    Raises AssertionError on the first failure."""
     T, n = R["tree"], cfg.n
     h = R["host"]
     cnt = np.bincount(R["labels"], minlength=n)
@@ -153,8 +154,9 @@ def check_all(R, cfg, n_sample=64, subtree_max=150000, log=print):
     assert np.array_equal(own + child, T["size"])
     # each particle's deepest node lies in its own group's subtree
     root_of = np.arange(lv.size)
-    for v in up:                     # parents precede children in canonical order
-        root_of[v] = root_of[p[v]]
+    for level in range(1, int(lv.max()) + 1 if lv.size else 1):   # level by level
+        at = np.flatnonzero(lv == level)
+        root_of[at] = root_of[p[at]]
     canon_root = np.full(n, -1, np.int64)
     canon_root[groups] = l0
     assert np.array_equal(root_of[dp[inn]], canon_root[R["labels"][inn]])
@@ -178,8 +180,9 @@ def check_all(R, cfg, n_sample=64, subtree_max=150000, log=print):
     pick = stratified(cnt[groups], groups, n_sample, cfg.min_group)
     log(f"{cfg.name}: {groups.size} groups, {lv.size} nodes; sampled sizes "
         f"{sorted(cnt[pick].tolist())}")
+    pick3 = [g for g in pick if closure_max is None or cnt[g] <= closure_max]
     with ThreadPoolExecutor(WORKERS) as ex:
-        r3 = list(ex.map(lambda g: check_3d(R, cfg, g), pick))
+        r3 = list(ex.map(lambda g: check_3d(R, cfg, g), pick3))
     bad3 = [(g, s, r) for ok, g, s, r in r3 if not ok]
     assert not bad3, bad3
     deep = [g for g in pick if cnt[g] <= subtree_max]
@@ -187,6 +190,6 @@ def check_all(R, cfg, n_sample=64, subtree_max=150000, log=print):
         r6 = list(ex.map(lambda g: check_subtree(R, cfg, g, root_of, canon_root), deep))
     bad6 = [b for r in r6 for b in r]
     assert not bad6, bad6[:10]
-    log(f"{cfg.name}: 3D checked on {len(pick)} groups (largest {cnt[pick].max()}), "
+    log(f"{cfg.name}: 3D checked on {len(pick3)} groups (largest {max(cnt[g] for g in pick3)}), "
         f"6D subtrees on {len(deep)} groups (largest {max(cnt[g] for g in deep)})")
-    return len(pick), len(deep)
+    return len(pick3), len(deep)

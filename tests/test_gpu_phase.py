@@ -152,3 +152,37 @@ def test_repeat_identical_and_forms_agree():
     c = rs.rs_phase_fof_batch(*t, cfg.box, lab, flags=rs.RS_PLAIN)
     for k in FIELDS + ("deepest",):
         assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
+
+
+def _fields_equal(a, b):
+    for k in ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "deepest"):
+        assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("flags", [rs.RS_BATCHED, rs.RS_LEARNED])
+def test_chunked_level_pipeline_equals_one_pass(flags, monkeypatch):
+    # the level pipeline over consecutive chunks of level-0 groups (what a
+    # device short of memory does) gives the same tree as one pass
+    from paper_2412_18629_amd import learn
+    cfg = synth.scaled(synth.CONFIGS["c32"], 400000)
+    arrs = [a.cuda() for a in synth.generate(cfg, 31)]
+    lab, _ = rs.rs_fof3d(*arrs[:3], cfg.box, cfg.link_len)
+    model = learn.load_model() if flags == rs.RS_LEARNED else None
+    one = rs.rs_phase_fof_batch(*arrs, cfg.box, lab, flags=flags, model=model)
+    monkeypatch.setenv("RS_DEBUG_CHUNK_MEMBERS", "3000")
+    chunked = rs.rs_phase_fof_batch(*arrs, cfg.box, lab, flags=flags, model=model)
+    monkeypatch.delenv("RS_DEBUG_CHUNK_MEMBERS")
+    _fields_equal(one, chunked)
+    assert int((one["size"] > 2048).sum()) > 3          # several large groups, several chunks
+
+
+def test_tree_overflow_rebuild_equals(monkeypatch):
+    # a search tree built into too small a buffer is rebuilt larger; same tree
+    cfg = synth.scaled(synth.CONFIGS["c32"], 300000)
+    arrs = [a.cuda() for a in synth.generate(cfg, 32)]
+    lab, _ = rs.rs_fof3d(*arrs[:3], cfg.box, cfg.link_len)
+    ref = rs.rs_phase_fof_batch(*arrs, cfg.box, lab)
+    monkeypatch.setenv("RS_DEBUG_TREE_ENTRIES", "64")
+    got = rs.rs_phase_fof_batch(*arrs, cfg.box, lab)
+    monkeypatch.delenv("RS_DEBUG_TREE_ENTRIES")
+    _fields_equal(ref, got)
