@@ -214,6 +214,7 @@ def main():
         print("no HIP device visible", file=sys.stderr)
         return 2
     rs.load()
+    tuning = rs.load_tuning()
     cfg = synth.CONFIGS[args.config]
     model = learn.load_model()
     dev = torch.device("cuda:0")
@@ -250,6 +251,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload_description(cfg), "form": args.form,
+                   "tuning": tuning["choice"] if tuning else "compiled defaults",
                    "groups": n_groups, "nodes": int(tree["level"].numel()),
                    "levels": tree["n_levels"],
                    "proposals_accepted": tree["n_accepted"],

@@ -201,6 +201,26 @@ int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out,
                           void* stream);
 
 /*
+ * Launch-shape tuning table (process-wide).  The batched form runs every
+ * recursion level in size-bucketed kernels; these knobs pick among the
+ * compiled launch shapes, and results are identical for every choice (only
+ * speed changes).  Knobs:
+ *   "small_threads_256"   threads per workgroup, nodes of 65..256 members:   128, 256
+ *   "small_threads_1024"  threads per workgroup, nodes of 257..1024 members: 256, 512, 1024
+ *   "small_threads_2048"  threads per workgroup, nodes of 1025..2048:        512, 1024
+ *   "xcd_chunk"           longest run of consecutive 64-member tiles one XCD
+ *                         takes in the large-node search kernels:           256, 1024, 4096
+ * rs_tune_set: RS_OK, or RS_EINVAL for an unknown knob or a value not in its
+ * list.  rs_tune_get: stores the current value, writes up to max_choices of
+ * the allowed values into choices (host, may be NULL) and returns how many
+ * there are, or RS_EINVAL.  rs_tune_name: name of knob `index` (0-based),
+ * NULL past the last.  Not to be changed while a library call runs.
+ */
+int rs_tune_set(const char* knob, int value);
+int rs_tune_get(const char* knob, int* value, int32_t* choices, int max_choices);
+const char* rs_tune_name(int index);
+
+/*
  * Releases the library's device workspaces on the current device.  The
  * library keeps grow-only workspaces between calls so repeated calls do not
  * allocate; a caller that needs the memory back (for example before working

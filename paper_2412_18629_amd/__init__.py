@@ -24,7 +24,8 @@ RS_MLP_NPARAM = 5825
 EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
             "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
-            "rs_sort_pairs_u64_i32", "rs_release_workspace")
+            "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_tune_set", "rs_tune_get",
+            "rs_tune_name")
 
 
 class RsError(RuntimeError):
@@ -80,6 +81,13 @@ def load():
     lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
     lib.rs_sort_pairs_u64_i32.argtypes = [P, P, P, P, i64, ctypes.c_int, P]
     lib.rs_release_workspace.argtypes = []
+    lib.rs_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int]
+    lib.rs_tune_set.restype = ctypes.c_int
+    lib.rs_tune_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
+    lib.rs_tune_get.restype = ctypes.c_int
+    lib.rs_tune_name.argtypes = [ctypes.c_int]
+    lib.rs_tune_name.restype = ctypes.c_char_p
     for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
                "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -140,6 +148,42 @@ def rs_sort_pairs(keys, vals, bits=64, stream=None):
                                      _dev(vals, torch.int32, "vals"), _dev(vo, torch.int32, "vals"),
                                      n, int(bits), _stream(stream)), "rs_sort_pairs_u64_i32")
     return ko, vo
+
+
+def tune_knobs():
+    """{knob: (current value, allowed values)} of the launch-shape table."""
+    lib = load()
+    out = {}
+    i = 0
+    while True:
+        name = lib.rs_tune_name(i)
+        if name is None:
+            return out
+        cur = ctypes.c_int(0)
+        ch = (ctypes.c_int32 * 8)()
+        k = lib.rs_tune_get(name, ctypes.byref(cur), ch, 8)
+        if k < 0:
+            raise RsError(k, "rs_tune_get")
+        out[name.decode()] = (int(cur.value), [int(ch[j]) for j in range(min(k, 8))])
+        i += 1
+
+
+def tune_set(knob, value):
+    _ck(load().rs_tune_set(knob.encode(), int(value)), f"rs_tune_set({knob})")
+
+
+def load_tuning(path=None):
+    """Apply a tuning table written by paper_2412_18629_amd.autotune (the
+    default table next to this package when present); returns it or None."""
+    import json
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    for knob, value in table["choice"].items():
+        tune_set(knob, value)
+    return table
 
 
 def rs_release_workspace():

@@ -210,6 +210,12 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
 void prof_begin(const char* name, hipStream_t st);
 void prof_end(const char* name, hipStream_t st, double units);
 
+// Tuning table: launch shapes chosen per size bucket by the autotuner.  Every
+// value is one of a small compiled set; results are the same for all of them.
+enum TuneKnob { TUNE_SMALL_NT_256, TUNE_SMALL_NT_1024, TUNE_SMALL_NT_2048, TUNE_XCD_CHUNK,
+                TUNE_N };
+int tune_get(TuneKnob k);
+
 // device-wide primitives (prims.hip)
 size_t scan_temp_bytes(int64_t n);
 int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* temp,

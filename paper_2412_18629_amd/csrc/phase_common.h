@@ -141,10 +141,12 @@ inline int xcd_chunk_grid(int n, int C) {
     const int g = XCDS * C;
     return (n + g - 1) / g * g;
 }
-// chunk length: whole rounds stay at least 64 so the XCDs finish together
+// chunk length: whole rounds stay at least 64 so the XCDs finish together;
+// the longest chunk comes from the tuning table
 inline int xcd_chunk(int ntiles) {
+    const int cap = tune_get(TUNE_XCD_CHUNK);
     int c = ntiles / (64 * XCDS);
-    return c < 1 ? 1 : (c > 1024 ? 1024 : c);
+    return c < 1 ? 1 : (c > cap ? cap : c);
 }
 
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st);

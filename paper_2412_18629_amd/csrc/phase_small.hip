@@ -419,14 +419,27 @@ static int launch_small(const SmallItem* items, int n_items, const Members& mb,
 // bucket b: 0 -> <= 64 members, 1 -> <= 256, 2 -> <= 1024, 3 -> <= 2048
 int small_bucket_of(int size) { return size <= 64 ? 0 : size <= 256 ? 1 : size <= 1024 ? 2 : 3; }
 
+// Threads per workgroup of buckets 1..3, from the tuning table (each value is
+// one of the compiled shapes; results do not depend on the choice).
 int run_small_bucket(int b, const SmallItem* items, int n_items, const Members& mb,
                      const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
                      hipStream_t st) {
     switch (b) {
         case 0: return launch_small<64, 64>(items, n_items, mb, nr, pp, deepest, st);
-        case 1: return launch_small<256, 256>(items, n_items, mb, nr, pp, deepest, st);
-        case 2: return launch_small<1024, 512>(items, n_items, mb, nr, pp, deepest, st);
-        default: return launch_small<SMALL_MAX, 1024>(items, n_items, mb, nr, pp, deepest, st);
+        case 1:
+            if (tune_get(TUNE_SMALL_NT_256) == 128)
+                return launch_small<256, 128>(items, n_items, mb, nr, pp, deepest, st);
+            return launch_small<256, 256>(items, n_items, mb, nr, pp, deepest, st);
+        case 2:
+            if (tune_get(TUNE_SMALL_NT_1024) == 256)
+                return launch_small<1024, 256>(items, n_items, mb, nr, pp, deepest, st);
+            if (tune_get(TUNE_SMALL_NT_1024) == 1024)
+                return launch_small<1024, 1024>(items, n_items, mb, nr, pp, deepest, st);
+            return launch_small<1024, 512>(items, n_items, mb, nr, pp, deepest, st);
+        default:
+            if (tune_get(TUNE_SMALL_NT_2048) == 512)
+                return launch_small<SMALL_MAX, 512>(items, n_items, mb, nr, pp, deepest, st);
+            return launch_small<SMALL_MAX, 1024>(items, n_items, mb, nr, pp, deepest, st);
     }
 }
 

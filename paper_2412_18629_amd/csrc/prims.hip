@@ -2,6 +2,8 @@
 // fills, and the per-device workspace.
 #include "common.h"
 
+#include <string.h>
+
 
 #include <map>
 #include <mutex>
@@ -20,6 +22,31 @@ static void* g_host_scratch[64];
 static size_t g_host_scratch_bytes[64];
 
 size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// tuning table
+// ---------------------------------------------------------------------------
+
+struct TuneDef {
+    const char* name;
+    int value;              // current value (compiled default until set)
+    int allowed[4];         // compiled choices, 0-terminated
+};
+static TuneDef g_tune[TUNE_N] = {
+    {"small_threads_256", 256, {128, 256, 0, 0}},
+    {"small_threads_1024", 512, {256, 512, 1024, 0}},
+    {"small_threads_2048", 1024, {512, 1024, 0, 0}},
+    {"xcd_chunk", 1024, {256, 1024, 4096, 0}},
+};
+
+int tune_get(TuneKnob k) { return g_tune[k].value; }
+
+static int tune_find(const char* name) {
+    if (!name) return -1;
+    for (int k = 0; k < TUNE_N; k++)
+        if (strcmp(name, g_tune[k].name) == 0) return k;
+    return -1;
+}
 
 static int current_device(int* dev) {
     RS_HIP(hipGetDevice(dev));
@@ -304,6 +331,34 @@ int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* temp,
 }  // namespace rs
 
 extern "C" {
+
+int rs_tune_set(const char* knob, int value) {
+    const int k = rs::tune_find(knob);
+    if (k < 0) return RS_EINVAL;
+    for (int v : rs::g_tune[k].allowed)
+        if (v != 0 && v == value) {
+            rs::g_tune[k].value = value;
+            return RS_OK;
+        }
+    return RS_EINVAL;
+}
+
+int rs_tune_get(const char* knob, int* value, int32_t* choices, int max_choices) {
+    const int k = rs::tune_find(knob);
+    if (k < 0 || !value) return RS_EINVAL;
+    *value = rs::g_tune[k].value;
+    int n = 0;
+    for (int v : rs::g_tune[k].allowed)
+        if (v != 0) {
+            if (choices && n < max_choices) choices[n] = v;
+            n++;
+        }
+    return n;
+}
+
+const char* rs_tune_name(int index) {
+    return (index >= 0 && index < rs::TUNE_N) ? rs::g_tune[index].name : nullptr;
+}
 
 int rs_profile_enable(int on) {
     std::lock_guard<std::mutex> g(rs::g_prof_mu);

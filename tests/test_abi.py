@@ -94,3 +94,14 @@ def test_sort_rejects_bad_arguments(n, bits, alias):
     rc = lib.rs_sort_pairs_u64_i32(a, b, ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), n,
                                    bits, None)
     assert rc == rs.RS_EINVAL
+
+
+def test_tuning_table_rejects_unknown_knobs_and_values():
+    knobs = rs.tune_knobs()
+    assert set(knobs) == {"small_threads_256", "small_threads_1024", "small_threads_2048",
+                          "xcd_chunk"}
+    for name, (cur, allowed) in knobs.items():
+        assert cur in allowed
+    lib = rs.load()
+    assert lib.rs_tune_set(b"no_such_knob", 1) == rs.RS_EINVAL
+    assert lib.rs_tune_set(b"xcd_chunk", 3) == rs.RS_EINVAL
