@@ -35,6 +35,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(cfg, form):
+    rs.load_tuning()                   # the launch shapes bench.py times
     dev = torch.device("cuda:0")
     arrs = synth.generate(cfg, 0, device=dev)
     torch.cuda.empty_cache()           # the generator's fp64 temporaries
