@@ -1,12 +1,12 @@
 """Training of the linking-length proposer on the GPU with the library's kernels.
 
 Training pairs come from the exact method itself: for every node of the
-hierarchy on seeded 256^3 workloads, (features, ln l) where l^2 is the exact
+hierarchy on seeded 256^3 workloads (seeds 100-199 for the shipped model), (features, ln l) where l^2 is the exact
 linking length the batched form chose.  The network is trained with the
 library's own forward / backward / Adam kernels (rs_mlp_train_step); this
 module only shuffles minibatch indices and moves tensors.
 
-    python -m paper_2412_18629_amd.learn --seeds 100-107 --out paper_2412_18629_amd/mlp_c256.bin
+    python -m paper_2412_18629_amd.learn --seeds 100-199 --out paper_2412_18629_amd/mlp_c256.bin
 """
 from __future__ import annotations
 
@@ -25,8 +25,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(HERE, "mlp_c256.bin")
 
 
-def collect(seeds, config="c256", device="cuda", verbose=True):
-    """(features [n, 24], ln l [n]) device tensors from the exact batched form."""
+def collect(seeds, config="c256", device="cuda", verbose=True, min_size=0):
+    """(features [n, 24], ln l [n]) device tensors from the exact batched form,
+    for nodes with more than min_size members."""
     cfg = synth.CONFIGS[config] if isinstance(config, str) else config
     xs, ys = [], []
     for seed in seeds:
@@ -35,7 +36,7 @@ def collect(seeds, config="c256", device="cuda", verbose=True):
         lab, _ = rs.rs_fof3d(*arrs[:3], cfg.box, cfg.link_len)
         tree = rs.rs_phase_fof_batch(*arrs, cfg.box, lab, cfg.min_group, cfg.min_sub, cfg.f,
                                      flags=rs.RS_BATCHED | rs.RS_FEATURES)
-        keep = tree["l2"] > 0
+        keep = (tree["l2"] > 0) & (tree["size"] > min_size)
         xs.append(tree["features"][keep].contiguous())
         ys.append((0.5 * torch.log(tree["l2"][keep].double())).float())
         if verbose:
@@ -106,12 +107,15 @@ def _seeds(spec):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--seeds", default="100-107")
+    ap.add_argument("--seeds", default="100-199")
     ap.add_argument("--config", default="c256")
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--min-size", type=int, default=0,
+                    help="train only on nodes with more members (the proposer is applied to "
+                         "nodes of more than 2048)")
     ap.add_argument("--out", default=DEFAULT_MODEL)
     args = ap.parse_args(argv)
-    X, y = collect(_seeds(args.seeds), args.config)
+    X, y = collect(_seeds(args.seeds), args.config, min_size=args.min_size)
     print(f"training on {X.shape[0]} (node, level) pairs", flush=True)
     mean, std, params, _ = train(X, y, epochs=args.epochs)
     save(args.out, mean, std, params)
