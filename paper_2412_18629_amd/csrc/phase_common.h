@@ -125,7 +125,12 @@ constexpr int64_t O32_LIMIT = (int64_t)1 << 30;
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,
                const PhaseParams& pp, std::vector<int32_t>* level_begin, bool* overflow,
-               hipStream_t st);
+               int32_t* n_entry_out, hipStream_t st);
+// refits the leaf and internal boxes to the members with d_i^2 <= l^2 (after
+// the select, before linking)
+int tree_refit_active(TreeBuf& tb, int32_t n_entry, const std::vector<int32_t>& level_begin,
+                      const Members& T, const int32_t* mnode, const LParam* prm,
+                      const PhaseParams& pp, const float* d2, hipStream_t st);
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Blocks are remapped so that every XCD runs consecutive chunks of C
 // tiles: neighbouring tiles, which read mostly the same candidate data, then

@@ -813,10 +813,11 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     std::vector<int32_t> tree_levels;
     // search tree; its buffers grow and the build is redone on overflow
     if (w->tb.cap_entry == 0) RS_TRY(tree_reserve(w, w->cap_m, w->cap_nodes, 1));
+    int32_t n_entry = 0;
     for (int64_t grow = 2;; grow *= 2) {
         bool tree_overflow = false;
         RS_TRY(tree_build(w->tb, w->root, w->kout, w->nodes, nv, w->T, w->mnode, w->prm, pp,
-                          &tree_levels, &tree_overflow, st));
+                          &tree_levels, &tree_overflow, &n_entry, st));
         if (!tree_overflow) break;
         if (grow > 1024) return RS_EINTERNAL;
         RS_TRY(tree_reserve(w, w->cap_m, w->cap_nodes, grow));
@@ -867,6 +868,8 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
         RS_HIP(hipGetLastError());
     }
     k_liota<<<gm, BT, 0, st>>>(M, w->par);
+    // only members with d_i^2 <= l^2 can link: shrink the boxes to them
+    RS_TRY(tree_refit_active(w->tb, n_entry, tree_levels, w->T, w->mnode, w->prm, pp, w->d2, st));
     prof_begin("phase_large_link", st);
     RS_TRY(tile_link(TA, tiles, w->d2, w->par, st));
     prof_end("phase_large_link", st, (double)M);

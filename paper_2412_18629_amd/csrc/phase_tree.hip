@@ -199,6 +199,41 @@ k_tree_leafbox(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict
     }
 }
 
+// leaf boxes over the members that can still link (d_i^2 <= l^2 of their
+// node); a leaf without any gets an empty box (lo = +inf, hi = -inf), which
+// every lower bound rejects.  Member ranges and leaf_of are unchanged.
+__global__ void __launch_bounds__(256)
+k_tree_leafbox_active(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict__ mnode,
+                      const LParam* __restrict__ prm, PhaseParams pp,
+                      const float* __restrict__ d2) {
+    const int lane = threadIdx.x & 63;
+    const int32_t e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= n_entry || tb.enode[e] >= 0) return;
+    const int32_t s = tb.estart[e], t = tb.eend[e];
+    const int32_t m = s + lane;
+    bool ok = m < t;
+    float c[6] = {0, 0, 0, 0, 0, 0};
+    if (ok) {
+        const LParam P = prm[mnode[m]];
+        ok = d2[m] <= P.l2;
+        c[0] = min_image(T.x[m] - P.rx, pp.L, pp.h);
+        c[1] = min_image(T.y[m] - P.ry, pp.L, pp.h);
+        c[2] = min_image(T.z[m] - P.rz, pp.L, pp.h);
+        c[3] = T.vx[m];
+        c[4] = T.vy[m];
+        c[5] = T.vz[m];
+    }
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        float lo = wmin(ok ? c[d] : __builtin_huge_valf());
+        float hi = wmax(ok ? c[d] : -__builtin_huge_valf());
+        if (lane == 0) {
+            tb.erec[16 * (int64_t)e + d] = lo;
+            tb.erec[16 * (int64_t)e + 6 + d] = hi;
+        }
+    }
+}
+
 // internal-node boxes of one level (children done before parents)
 __global__ void __launch_bounds__(256)
 k_tree_nodebox(int32_t node_begin, int32_t node_end, TreeBuf tb) {
@@ -463,8 +498,9 @@ __global__ void k_tree_roots(int nv, const LNode* __restrict__ nodes, TreeBuf tb
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,
                const PhaseParams& pp, std::vector<int32_t>* level_begin, bool* overflow,
-               hipStream_t st) {
+               int32_t* n_entry_out, hipStream_t st) {
     *overflow = false;
+    *n_entry_out = 0;
     int32_t* hc = nullptr;
     RS_TRY(host_scratch((void**)&hc, 64));
     RS_HIP(hipMemsetAsync(tb.n_entry, 0, sizeof(int32_t), st));
@@ -502,6 +538,25 @@ int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* n
     // internal boxes, deepest level first
     for (int l = (int)level_begin->size() - 2; l >= 0; l--) {
         int32_t lb = (*level_begin)[l], le = (*level_begin)[l + 1];
+        if (le > lb) {
+            k_tree_nodebox<<<(le - lb + 3) / 4, 256, 0, st>>>(lb, le, tb);
+            RS_HIP(hipGetLastError());
+        }
+    }
+    *n_entry_out = n_entry;
+    return RS_OK;
+}
+
+int tree_refit_active(TreeBuf& tb, int32_t n_entry, const std::vector<int32_t>& level_begin,
+                      const Members& T, const int32_t* mnode, const LParam* prm,
+                      const PhaseParams& pp, const float* d2, hipStream_t st) {
+    if (n_entry > 0) {
+        k_tree_leafbox_active<<<(n_entry + 3) / 4, 256, 0, st>>>(n_entry, tb, T, mnode, prm, pp,
+                                                                 d2);
+        RS_HIP(hipGetLastError());
+    }
+    for (int l = (int)level_begin.size() - 2; l >= 0; l--) {
+        int32_t lb = level_begin[l], le = level_begin[l + 1];
         if (le > lb) {
             k_tree_nodebox<<<(le - lb + 3) / 4, 256, 0, st>>>(lb, le, tb);
             RS_HIP(hipGetLastError());
