@@ -50,8 +50,8 @@ FLAGS = {"learned": rs.RS_LEARNED, "batched": rs.RS_BATCHED, "plain": rs.RS_PLAI
 # is only used while these sources are unchanged)
 KERNEL_SYMBOL = {
     "fof3d_link": ("void rs::k_link<", ["fof3d.hip", "common.h"]),
-    "phase_large_nn": ("rs::k_tree_nn(", ["phase_tree.hip", "phase_common.h", "common.h"]),
-    "phase_large_link": ("rs::k_tile_link(", ["phase_tile.hip", "phase_common.h", "common.h"]),
+    "phase_large_nn": ("void rs::k_tree_nn<", ["phase_tree.hip", "phase_common.h", "common.h"]),
+    "phase_large_link": ("void rs::k_tile_link<", ["phase_tile.hip", "phase_common.h", "common.h"]),
     "phase_small": ("void rs::k_small_subtree<",
                     ["phase_small.hip", "phase_common.h", "common.h"]),
 }
@@ -245,6 +245,7 @@ def main():
     avg_ms = tot_ms / max(launches, 1)
     bytes_per_launch = KERNEL_BYTES[dom] * units / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic(dom, cfg.name)
     line = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -257,10 +258,15 @@ def main():
                    "proposals_accepted": tree["n_accepted"],
                    "proposals_fallback": tree["n_fallback"],
                    "groups_per_s": n_groups / (ms / 1000.0),
+                   "nodes_per_s": int(tree["level"].numel()) / (ms / 1000.0),
+                   "acceptance_rate": (tree["n_accepted"] /
+                                       max(1, tree["n_accepted"] + tree["n_fallback"])),
                    "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, cfg.name),
+                     "traffic": traffic,
+                     "traffic_gbs": (traffic / (avg_ms / 1000.0) / 1e9
+                                     if traffic is not None and avg_ms > 0 else None),
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
