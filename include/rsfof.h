@@ -106,7 +106,8 @@ typedef struct rs_tree {
     float* sv2;          /* [n_nodes] velocity dispersion sigma_v^2, (km/s)^2 */
     int32_t* deepest;    /* [n_particles] deepest node containing the particle, or -1 */
     int64_t n_accepted;  /* RS_LEARNED: nodes whose proposed bracket held */
-    int64_t n_fallback;  /* RS_LEARNED: nodes that fell back to the full search */
+    int64_t n_fallback;  /* RS_LEARNED: nodes whose bracket was rejected and which
+                            were completed by the exact refinement */
     int64_t n_levels;    /* number of levels (max level + 1), 0 if no nodes */
     float* features;     /* [n_nodes * RS_NFEAT] with RS_FEATURES, else NULL */
 } rs_tree;
@@ -145,9 +146,10 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z,
                        void* stream);
 
 /*
- * Linking-length proposer (SURVEY-level "learned part"; it never decides a
- * result: RS_LEARNED verifies every proposal exactly and falls back to the
- * full nearest-neighbour search).  All pointers are device pointers.
+ * Linking-length proposer: a small network that predicts ln l of a node from
+ * 24 summary features.  It never decides a result: RS_LEARNED verifies every
+ * proposal exactly and completes rejected ones with the exact search.  All
+ * pointers are device pointers.
  *
  * rs_mlp_forward:   y[n] = MLP(params, X[n][RS_NFEAT]) in fp32 (X standardised).
  * rs_mlp_grad:      grad[RS_MLP_NPARAM] and loss = mean((y - t)^2) over n samples.
