@@ -80,11 +80,22 @@ def _pmc_rows(path, counter):
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, copy_bytes, command, out_path):
+# vector ALU: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies its SIMD
+# for 4 cycles (SQ_ACTIVE_INST_VALU counts in those 4-cycle units);
+# GRBM_GUI_ACTIVE is summed over the 8 XCDs
+N_SIMD = 1024
+N_XCD = 8
+
+
+def pmc_summary(fetch_csv, write_csv, copy_bytes, command, out_path, valu_csv=None):
     """Per-launch HBM traffic of the instrumented kernels from a FETCH_SIZE run
     and a WRITE_SIZE run of this script (with --probe-copy), each counter
-    scaled by what it reads for the plain device copy of known size."""
+    scaled by what it reads for the plain device copy of known size; with a
+    third run of SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE, the fraction of the
+    vector ALU issue slots each kernel used."""
     fe, wr = _pmc_rows(fetch_csv, "FETCH_SIZE"), _pmc_rows(write_csv, "WRITE_SIZE")
+    va = _pmc_rows(valu_csv, "SQ_ACTIVE_INST_VALU") if valu_csv else {}
+    gr = _pmc_rows(valu_csv, "GRBM_GUI_ACTIVE") if valu_csv else {}
 
     def probe(rows):
         vals = sorted(v for n, v in rows.values() if "copyBuffer" in n)[-3:]
@@ -103,13 +114,17 @@ def pmc_summary(fetch_csv, write_csv, copy_bytes, command, out_path):
         res["kernels"][k] = {"symbol": sym, "launches": len(f), "fetch_kib": f, "write_kib": w,
                              "hbm_bytes_per_launch": float(np.mean(per)),
                              "sources_sha256": source_digest(k)}
+        inst = sum(v for n, v in va.values() if n.startswith(sym))
+        cyc = sum(v for n, v in gr.values() if n.startswith(sym))
+        if inst > 0 and cyc > 0:
+            res["kernels"][k]["valu_busy"] = inst * 4.0 / (cyc / N_XCD * N_SIMD)
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
     return res
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed PMC summary, or None when there
+def measured_pmc(kernel, workload, field):
+    """A field of the committed PMC summary for this kernel, or None when there
     is none for this kernel and workload or the kernel's sources changed."""
     try:
         with open(PMC_SUMMARY) as fh:
@@ -121,7 +136,7 @@ def measured_traffic(kernel, workload):
         return None
     if ent.get("sources_sha256") != source_digest(kernel):
         return None
-    return ent["hbm_bytes_per_launch"]
+    return ent.get(field)
 
 
 def workload_description(cfg):
@@ -199,11 +214,15 @@ def main():
                     help="write the per-launch traffic summary from two rocprofv3 --pmc "
                          "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) of a run "
                          "with --probe-copy MIB, then exit")
+    ap.add_argument("--pmc-valu", default=None, metavar="VALU_CSV",
+                    help="with --pmc-summary: counter_collection.csv of a run with "
+                         "SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE")
     ap.add_argument("--pmc-command", default="", help="command recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
         fcsv, wcsv, mib = args.pmc_summary
-        res = pmc_summary(fcsv, wcsv, int(mib) << 20, args.pmc_command, PMC_SUMMARY)
+        res = pmc_summary(fcsv, wcsv, int(mib) << 20, args.pmc_command, PMC_SUMMARY,
+                          args.pmc_valu)
         print(json.dumps({k: v["hbm_bytes_per_launch"] for k, v in res["kernels"].items()}))
         return 0
     if args.gpus != 1:
@@ -245,7 +264,7 @@ def main():
     avg_ms = tot_ms / max(launches, 1)
     bytes_per_launch = KERNEL_BYTES[dom] * units / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
-    traffic = measured_traffic(dom, cfg.name)
+    traffic = measured_pmc(dom, cfg.name, "hbm_bytes_per_launch")
     line = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -267,6 +286,7 @@ def main():
                      "traffic": traffic,
                      "traffic_gbs": (traffic / (avg_ms / 1000.0) / 1e9
                                      if traffic is not None and avg_ms > 0 else None),
+                     "valu_busy": measured_pmc(dom, cfg.name, "valu_busy"),
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
