@@ -189,6 +189,25 @@ void tree_release(rs_tree* t) {
     free(t);
 }
 
+// One side stream (default priority) and two ordering events per device,
+// created on first use and kept for the process.
+static int side_stream(hipStream_t* s, hipEvent_t* ready, hipEvent_t* done) {
+    static hipStream_t g_s[64];
+    static hipEvent_t g_r[64], g_d[64];
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return RS_EDEVICE;
+    if (!g_s[dev]) {
+        RS_HIP(hipStreamCreateWithFlags(&g_s[dev], hipStreamNonBlocking));
+        RS_HIP(hipEventCreateWithFlags(&g_r[dev], hipEventDisableTiming));
+        RS_HIP(hipEventCreateWithFlags(&g_d[dev], hipEventDisableTiming));
+    }
+    *s = g_s[dev];
+    *ready = g_r[dev];
+    *done = g_d[dev];
+    return RS_OK;
+}
+
 static int phase_attempt(const float* x, const float* y, const float* z, const float* vx,
                          const float* vy, const float* vz, int64_t n, float L,
                          const int32_t* lab, int32_t min_group, const PhaseParams& pp,
@@ -388,10 +407,22 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
             }
         }
     } else {
-        for (int b = 3; b >= 0; b--)
-            RS_TRY(run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, st));
+        // The level-0 subtrees of the small groups run on a side stream while
+        // the large-node levels run on the caller's: they read the level-0
+        // members only, write disjoint particles' deepest nodes and take node
+        // record slots atomically, so the two overlap freely and the result
+        // does not depend on their interleaving.
+        hipStream_t s2 = nullptr;
+        hipEvent_t ready = nullptr, done = nullptr;
+        RS_TRY(side_stream(&s2, &ready, &done));
+        RS_HIP(hipEventRecord(ready, st));
+        RS_HIP(hipStreamWaitEvent(s2, ready, 0));
+        int rc = RS_OK;
+        for (int b = 3; b >= 0 && rc == RS_OK; b--)
+            rc = run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, s2,
+                                  "phase_small_level0");
         size_t li = 0;
-        while (li < large.size()) {
+        while (rc == RS_OK && li < large.size()) {
             std::vector<ChildOut> cur, nxt;
             int64_t sum = 0;
             while (li < large.size() && (cur.empty() || sum + large[li].size <= mcap)) {
@@ -399,12 +430,23 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
                 cur.push_back(large[li++]);
             }
             const Members* in = &A;
-            while (!cur.empty()) {
-                RS_TRY(large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc,
-                                   &n_fb, st));
+            while (rc == RS_OK && !cur.empty()) {
+                rc = large_level(&lw, cur, *in, x, y, z, pp, nr, deepest, &nxt, &n_acc, &n_fb,
+                                 st);
                 cur.swap(nxt);
                 in = &lw.SN;
             }
+        }
+        // join (also on failure, so nothing runs on after the call returns)
+        if (hipEventRecord(done, s2) != hipSuccess ||
+            hipStreamWaitEvent(st, done, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s2);
+            return rc != RS_OK ? rc : RS_EDEVICE;
+        }
+        if (rc != RS_OK) {
+            (void)hipStreamSynchronize(s2);
+            return rc;
         }
     }
 

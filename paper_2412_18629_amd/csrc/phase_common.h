@@ -210,7 +210,8 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
 int mlp_infer(const float* model_dev, int nv, const float* feat, float* out, hipStream_t st);
 int run_small_bucket(int b, const SmallItem* items, int n_items, const Members& mb,
                      const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
-                     hipStream_t st);
+                     hipStream_t st,
+                     const char* timer = "phase_small");
 int small_bucket_of(int size);
 
 RS_DEV int64_t select_rank(int64_t n, int64_t ppm) {

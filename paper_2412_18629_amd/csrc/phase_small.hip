@@ -402,17 +402,17 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
 template <int MAXN, int NT>
 static int launch_small(const SmallItem* items, int n_items, const Members& mb,
                         const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
-                        hipStream_t st) {
+                        hipStream_t st, const char* timer) {
     if (n_items <= 0) return RS_OK;
     size_t lds = small_lds_bytes(MAXN, pp.min_sub);
     auto kern = pp.want_feat ? k_small_subtree<MAXN, NT, true> : k_small_subtree<MAXN, NT, false>;
     RS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     unsigned grid = (unsigned)(n_items < (1 << 20) ? n_items : (1 << 20));
-    prof_begin("phase_small", st);
+    prof_begin(timer, st);
     kern<<<grid, NT, lds, st>>>(items, n_items, mb, nr, pp, deepest);
     RS_HIP(hipGetLastError());
-    prof_end("phase_small", st, 0.0);
+    prof_end(timer, st, 0.0);
     return RS_OK;
 }
 
@@ -423,23 +423,23 @@ int small_bucket_of(int size) { return size <= 64 ? 0 : size <= 256 ? 1 : size <
 // one of the compiled shapes; results do not depend on the choice).
 int run_small_bucket(int b, const SmallItem* items, int n_items, const Members& mb,
                      const NodeRec& nr, const PhaseParams& pp, int32_t* deepest,
-                     hipStream_t st) {
+                     hipStream_t st, const char* timer) {
     switch (b) {
-        case 0: return launch_small<64, 64>(items, n_items, mb, nr, pp, deepest, st);
+        case 0: return launch_small<64, 64>(items, n_items, mb, nr, pp, deepest, st, timer);
         case 1:
             if (tune_get(TUNE_SMALL_NT_256) == 128)
-                return launch_small<256, 128>(items, n_items, mb, nr, pp, deepest, st);
-            return launch_small<256, 256>(items, n_items, mb, nr, pp, deepest, st);
+                return launch_small<256, 128>(items, n_items, mb, nr, pp, deepest, st, timer);
+            return launch_small<256, 256>(items, n_items, mb, nr, pp, deepest, st, timer);
         case 2:
             if (tune_get(TUNE_SMALL_NT_1024) == 256)
-                return launch_small<1024, 256>(items, n_items, mb, nr, pp, deepest, st);
+                return launch_small<1024, 256>(items, n_items, mb, nr, pp, deepest, st, timer);
             if (tune_get(TUNE_SMALL_NT_1024) == 1024)
-                return launch_small<1024, 1024>(items, n_items, mb, nr, pp, deepest, st);
-            return launch_small<1024, 512>(items, n_items, mb, nr, pp, deepest, st);
+                return launch_small<1024, 1024>(items, n_items, mb, nr, pp, deepest, st, timer);
+            return launch_small<1024, 512>(items, n_items, mb, nr, pp, deepest, st, timer);
         default:
             if (tune_get(TUNE_SMALL_NT_2048) == 512)
-                return launch_small<SMALL_MAX, 512>(items, n_items, mb, nr, pp, deepest, st);
-            return launch_small<SMALL_MAX, 1024>(items, n_items, mb, nr, pp, deepest, st);
+                return launch_small<SMALL_MAX, 512>(items, n_items, mb, nr, pp, deepest, st, timer);
+            return launch_small<SMALL_MAX, 1024>(items, n_items, mb, nr, pp, deepest, st, timer);
     }
 }
 
