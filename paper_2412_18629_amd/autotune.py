@@ -31,9 +31,9 @@ DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
 # the wall time of the whole 6D call, which decides (the level-0 small
 # subtrees overlap the large-node levels, so their own span is not exclusive)
 KNOB_KERNELS = {
-    "small_threads_256": ("phase_small", "phase_small_level0"),
-    "small_threads_1024": ("phase_small", "phase_small_level0"),
-    "small_threads_2048": ("phase_small", "phase_small_level0"),
+    "small_threads_256": ("phase_small", "phase_small_level0", "phase_small_children"),
+    "small_threads_1024": ("phase_small", "phase_small_level0", "phase_small_children"),
+    "small_threads_2048": ("phase_small", "phase_small_level0", "phase_small_children"),
     "xcd_chunk": ("phase_large_nn", "phase_large_nn_fallback", "phase_large_link"),
 }
 FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "deepest")

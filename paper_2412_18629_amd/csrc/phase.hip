@@ -189,22 +189,23 @@ void tree_release(rs_tree* t) {
     free(t);
 }
 
-// One side stream (default priority) and two ordering events per device,
-// created on first use and kept for the process.
-static int side_stream(hipStream_t* s, hipEvent_t* ready, hipEvent_t* done) {
-    static hipStream_t g_s[64];
-    static hipEvent_t g_r[64], g_d[64];
+// Side streams (default priority) and ordering events per device, created on
+// first use and kept for the process.  Stream 0 takes the level-0 small
+// subtrees, stream 1 the small children of each large-node level.
+static int side_stream(int which, hipStream_t* s, hipEvent_t* ready, hipEvent_t* done) {
+    static hipStream_t g_s[64][2];
+    static hipEvent_t g_r[64][2], g_d[64][2];
     int dev = 0;
     RS_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return RS_EDEVICE;
-    if (!g_s[dev]) {
-        RS_HIP(hipStreamCreateWithFlags(&g_s[dev], hipStreamNonBlocking));
-        RS_HIP(hipEventCreateWithFlags(&g_r[dev], hipEventDisableTiming));
-        RS_HIP(hipEventCreateWithFlags(&g_d[dev], hipEventDisableTiming));
+    if (dev < 0 || dev >= 64 || which < 0 || which > 1) return RS_EDEVICE;
+    if (!g_s[dev][which]) {
+        RS_HIP(hipStreamCreateWithFlags(&g_s[dev][which], hipStreamNonBlocking));
+        RS_HIP(hipEventCreateWithFlags(&g_r[dev][which], hipEventDisableTiming));
+        RS_HIP(hipEventCreateWithFlags(&g_d[dev][which], hipEventDisableTiming));
     }
-    *s = g_s[dev];
-    *ready = g_r[dev];
-    *done = g_d[dev];
+    *s = g_s[dev][which];
+    *ready = g_r[dev][which];
+    *done = g_d[dev][which];
     return RS_OK;
 }
 
@@ -414,7 +415,9 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         // does not depend on their interleaving.
         hipStream_t s2 = nullptr;
         hipEvent_t ready = nullptr, done = nullptr;
-        RS_TRY(side_stream(&s2, &ready, &done));
+        RS_TRY(side_stream(0, &s2, &ready, &done));
+        RS_TRY(side_stream(1, &lw.side, &lw.side_ready, &lw.side_done));
+        lw.side_pending = false;
         RS_HIP(hipEventRecord(ready, st));
         RS_HIP(hipStreamWaitEvent(s2, ready, 0));
         int rc = RS_OK;
@@ -439,13 +442,16 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         }
         // join (also on failure, so nothing runs on after the call returns)
         if (hipEventRecord(done, s2) != hipSuccess ||
-            hipStreamWaitEvent(st, done, 0) != hipSuccess) {
+            hipStreamWaitEvent(st, done, 0) != hipSuccess ||
+            (lw.side_pending && hipStreamWaitEvent(st, lw.side_done, 0) != hipSuccess)) {
             (void)hipGetLastError();
             (void)hipStreamSynchronize(s2);
+            (void)hipStreamSynchronize(lw.side);
             return rc != RS_OK ? rc : RS_EDEVICE;
         }
         if (rc != RS_OK) {
             (void)hipStreamSynchronize(s2);
+            (void)hipStreamSynchronize(lw.side);
             return rc;
         }
     }

@@ -193,6 +193,11 @@ struct LargeWork {
     int32_t* lcnt;       // [2 * cap_nodes] bracket counts #(<= lo), #(<= hi)
     int32_t* lstat;      // [4] accepted, fell back
     const float* model;  // device copy of the proposer, or NULL (exact search)
+    // small children of a level run on `side` (when set) while the next level
+    // proceeds; side_done marks their end, side_pending that one is in flight
+    hipStream_t side = nullptr;
+    hipEvent_t side_ready = nullptr, side_done = nullptr;
+    bool side_pending = false;
 };
 
 size_t large_work_bytes(int64_t m, int32_t min_sub);

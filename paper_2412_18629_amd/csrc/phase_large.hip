@@ -742,8 +742,20 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
     RS_HIP(hipMemcpyAsync(hb, w->bcount, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
     int cnts[4] = {hb[0], hb[1], hb[2], hb[3]};
+    hipStream_t ls = st;
+    if (w->side) {
+        // on the side stream, after everything the caller's stream queued
+        RS_HIP(hipEventRecord(w->side_ready, st));
+        RS_HIP(hipStreamWaitEvent(w->side, w->side_ready, 0));
+        ls = w->side;
+    }
     for (int b = 3; b >= 0; b--)
-        RS_TRY(run_small_bucket(b, w->buckets + b * w->cap_small, cnts[b], mb, nr, pp, deepest, st));
+        RS_TRY(run_small_bucket(b, w->buckets + b * w->cap_small, cnts[b], mb, nr, pp, deepest, ls,
+                                w->side ? "phase_small_children" : "phase_small"));
+    if (w->side) {
+        RS_HIP(hipEventRecord(w->side_done, w->side));
+        w->side_pending = true;
+    }
     return RS_OK;
 }
 
@@ -876,6 +888,8 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     k_lflat<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk);
     k_lstat<<<gm, BT, 0, st>>>(M, w->par, w->T.idx, w->cnt, w->mpk);
     RS_HIP(hipMemsetAsync(w->ctr, 0, sizeof(LCounters), st));
+    // the previous level's small children may still read the child buffers
+    if (w->side_pending) RS_HIP(hipStreamWaitEvent(st, w->side_done, 0));
     k_lchild<<<gm, BT, 0, st>>>(M, w->par, w->cnt, w->mpk, w->mnode, w->nodes, pp, nr, w->cslot,
                                 w->coff, w->cfill, w->cclass, w->ctr, w->small_items,
                                 w->large_out, w->cap_m);
