@@ -210,6 +210,10 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
                 int64_t nx = cx + dx;
                 nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
                 uint64_t nkey = (uint64_t)((nz * nc + ny) * nc + nx);
+                // octants are numbered in cell-key order: a cell with a smaller
+                // key holds only earlier octants, whose pairs with this one are
+                // taken from their side
+                if (nkey < cell) continue;
                 int32_t cid = hash_find(A.hk, A.hv, A.mask, nkey);
                 if (cid < 0) continue;
                 int32_t b0 = A.cell_oct[cid], b1 = A.cell_oct[cid + 1];
