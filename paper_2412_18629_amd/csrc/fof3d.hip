@@ -9,28 +9,22 @@
 //              octant are linked without a test (auto-link).
 //   2. sort:   key/index radix sort -> cell-sorted order; positions are
 //              gathered into sorted SoA arrays (coalesced reads later).
-//   3. tables: occupied octants and cells are enumerated by scans; an
-//              open-addressing hash maps a cell key to its octant range.
+//   3. tables: occupied octants and cells are enumerated by scans.  Cell
+//              keys are x-fastest, so the occupied cells of one (y, z) row
+//              are a sorted run; a dense row table gives each row's run
+//              (when the grid has few rows for the particle count, else the
+//              run is found by binary search over all cell keys).
 //   4. link:   union-find over sorted slots.  An octant is one element
 //              (its first slot); octant pairs in the 27-cell neighbourhood
 //              are tested with early exit on the first linked pair, and
 //              skipped when already in one component.
 //   5. labels: flatten, smallest original index per root, scatter to the
 //              caller's label array.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rs {
-
-static constexpr uint64_t HASH_EMPTY = ~0ull;
-
-RS_DEV uint64_t mix64(uint64_t k) {
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdull;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ull;
-    k ^= k >> 33;
-    return k;
-}
 
 struct Grid3 {
     int64_t nc;        // cells per axis
@@ -133,43 +127,32 @@ __global__ void k_parent_init(int64_t n, const int32_t* __restrict__ oflag,
     parent[s] = oct_start[o];
 }
 
-__global__ void k_hash_insert(const uint64_t* __restrict__ cell_key, int32_t n_cell,
-                              uint64_t* __restrict__ hk, int32_t* __restrict__ hv,
-                              uint64_t mask) {
-    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cell) return;
-    uint64_t k = cell_key[c];
-    uint64_t slot = mix64(k) & mask;
-    for (;;) {
-        unsigned long long prev = atomicCAS((unsigned long long*)(hk + slot),
-                                            (unsigned long long)HASH_EMPTY,
-                                            (unsigned long long)k);
-        if (prev == HASH_EMPTY || prev == k) {
-            hv[slot] = c;
-            return;
-        }
-        slot = (slot + 1) & mask;
+// first index in [b, e) whose key is >= k (keys ascending)
+RS_DEV int32_t lower_bound_u64(const uint64_t* __restrict__ keys, int32_t b, int32_t e,
+                               uint64_t k) {
+    while (b < e) {
+        const int32_t m = b + ((e - b) >> 1);
+        if (keys[m] < k) b = m + 1;
+        else e = m;
     }
+    return b;
 }
 
-RS_DEV int32_t hash_find(const uint64_t* __restrict__ hk, const int32_t* __restrict__ hv,
-                         uint64_t mask, uint64_t k) {
-    uint64_t slot = mix64(k) & mask;
-    for (;;) {
-        uint64_t q = hk[slot];
-        if (q == k) return hv[slot];
-        if (q == HASH_EMPTY) return -1;
-        slot = (slot + 1) & mask;
-    }
+// row_start[r] = first cell whose row (key / nc) is >= r, for r in [0, rows]
+__global__ void k_row_start(const uint64_t* __restrict__ cell_key, int32_t n_cell, int64_t nc,
+                            int64_t rows, int32_t* __restrict__ row_start) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r > rows) return;
+    row_start[r] = lower_bound_u64(cell_key, 0, n_cell, (uint64_t)r * (uint64_t)nc);
 }
 
 struct LinkArgs {
     const int32_t* oct_start;   // [n_oct + 1]
     const uint8_t* oct_bits;    // [n_oct]
     const int32_t* cell_oct;    // [n_cell + 1]
-    const uint64_t* hk;
-    const int32_t* hv;
-    uint64_t mask;
+    const uint64_t* cell_key;   // [n_cell], ascending
+    const int32_t* row_start;   // [nc^2 + 1], or null: rows found by binary search
+    int32_t n_cell;
     const uint64_t* keys;       // sorted keys
     const float *sx, *sy, *sz;  // sorted positions
     int32_t* parent;
@@ -177,80 +160,122 @@ struct LinkArgs {
     Grid3 g;
 };
 
+// cells of row rr (cell indices [b, e))
+RS_DEV void row_cells(const LinkArgs& A, uint64_t rr, int32_t& b, int32_t& e) {
+    if (A.row_start) {
+        b = A.row_start[rr];
+        e = A.row_start[rr + 1];
+    } else {
+        const uint64_t nc = (uint64_t)A.g.nc;
+        b = lower_bound_u64(A.cell_key, 0, A.n_cell, rr * nc);
+        e = lower_bound_u64(A.cell_key, b, A.n_cell, (rr + 1) * nc);
+    }
+}
+
+// test octant a (slots [s0, s1), octant bits oa) against every later octant
+// of cell c, which sits at offset (dx, dy, dz) cells from a's cell
+// `ra` is a member of a's component (its last known root): finding from it
+// is a short walk, and it is updated to the current root on every use
+template <bool AUTOLINK>
+RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int oa, int32_t c,
+                      int dx, int dy, int dz, int32_t& ra) {
+    const Grid3& g = A.g;
+    const int32_t b0 = A.cell_oct[c], b1 = A.cell_oct[c + 1];
+    for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
+        if (g.octfilter) {
+            const int ob = A.oct_bits[b];
+            const int ddx = 2 * dx + (ob & 1) - (oa & 1);
+            const int ddy = 2 * dy + ((ob >> 1) & 1) - ((oa >> 1) & 1);
+            const int ddz = 2 * dz + (ob >> 2) - (oa >> 2);
+            if (ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 || ddz == -3)
+                continue;
+        }
+        const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
+        if (AUTOLINK) {
+            ra = uf_find(A.parent, ra);
+            const int32_t rb = uf_find(A.parent, t0);
+            if (ra == rb) continue;
+            bool hit = false;
+            for (int32_t i = s0; i < s1 && !hit; i++) {
+                const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+                for (int32_t j = t0; j < t1; j++) {
+                    if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2) {
+                        hit = true;
+                        break;
+                    }
+                }
+            }
+            if (hit) uf_unite(A.parent, ra, rb);
+        } else {
+            for (int32_t i = s0; i < s1; i++) {
+                const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+                for (int32_t j = t0; j < t1; j++)
+                    if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2)
+                        uf_unite(A.parent, i, j);
+            }
+        }
+    }
+}
+
 // one thread per octant: test it against every later octant in the
-// 27-cell neighbourhood
+// 27-cell neighbourhood.  Octants are numbered in cell-key order, so cells
+// with a smaller key (among them every cell of an earlier row) hold only
+// earlier octants, whose pairs with this one are taken from their side.
 template <bool AUTOLINK>
 __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
-    int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= A.n_oct) return;
-    const Grid3 g = A.g;
-    int32_t s0 = A.oct_start[a], s1 = A.oct_start[a + 1];
-    uint64_t cell = A.keys[s0] >> 3;
-    int oa = A.oct_bits[a];
-    int64_t nc = g.nc;
-    int64_t cx = (int64_t)(cell % (uint64_t)nc);
-    int64_t cy = (int64_t)((cell / (uint64_t)nc) % (uint64_t)nc);
-    int64_t cz = (int64_t)(cell / ((uint64_t)nc * (uint64_t)nc));
+    const Grid3& g = A.g;
+    const int32_t s0 = A.oct_start[a], s1 = A.oct_start[a + 1];
+    const uint64_t cell = A.keys[s0] >> 3;
+    const int oa = A.oct_bits[a];
+    const int64_t nc = g.nc;
+    const int64_t cx = (int64_t)(cell % (uint64_t)nc);
+    const uint64_t row = cell / (uint64_t)nc;
+    const int64_t cy = (int64_t)(row % (uint64_t)nc);
+    const int64_t cz = (int64_t)(row / (uint64_t)nc);
 
     if (!AUTOLINK) {
         for (int32_t i = s0; i < s1; i++) {
-            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+            const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
             for (int32_t j = i + 1; j < s1; j++)
                 if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2)
                     uf_unite(A.parent, i, j);
         }
     }
+    int32_t ra = s0;
+    // x - 1 .. x + 1 are one contiguous key range unless x wraps
+    const bool inner = nc >= 3 && cx >= 1 && cx <= nc - 2;
     for (int dz = -1; dz <= 1; dz++) {
         int64_t nz = cz + dz;
         nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
         for (int dy = -1; dy <= 1; dy++) {
             int64_t ny = cy + dy;
             ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
-            for (int dx = -1; dx <= 1; dx++) {
-                int64_t nx = cx + dx;
-                nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
-                uint64_t nkey = (uint64_t)((nz * nc + ny) * nc + nx);
-                // octants are numbered in cell-key order: a cell with a smaller
-                // key holds only earlier octants, whose pairs with this one are
-                // taken from their side
-                if (nkey < cell) continue;
-                int32_t cid = hash_find(A.hk, A.hv, A.mask, nkey);
-                if (cid < 0) continue;
-                int32_t b0 = A.cell_oct[cid], b1 = A.cell_oct[cid + 1];
-                for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
-                    if (g.octfilter) {
-                        int ob = A.oct_bits[b];
-                        int ddx = 2 * dx + (ob & 1) - (oa & 1);
-                        int ddy = 2 * dy + ((ob >> 1) & 1) - ((oa >> 1) & 1);
-                        int ddz = 2 * dz + (ob >> 2) - (oa >> 2);
-                        if (ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 ||
-                            ddz == -3)
-                            continue;
-                    }
-                    int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
-                    if (AUTOLINK) {
-                        if (uf_find(A.parent, s0) == uf_find(A.parent, t0)) continue;
-                        bool hit = false;
-                        for (int32_t i = s0; i < s1 && !hit; i++) {
-                            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
-                            for (int32_t j = t0; j < t1; j++) {
-                                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L,
-                                                g.h) <= g.ll2) {
-                                    hit = true;
-                                    break;
-                                }
-                            }
-                        }
-                        if (hit) uf_unite(A.parent, s0, t0);
-                    } else {
-                        for (int32_t i = s0; i < s1; i++) {
-                            float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
-                            for (int32_t j = t0; j < t1; j++)
-                                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L,
-                                                g.h) <= g.ll2)
-                                    uf_unite(A.parent, i, j);
-                        }
-                    }
+            const uint64_t rr = (uint64_t)(nz * nc + ny);
+            if (rr < row) continue;
+            int32_t rb, re;
+            row_cells(A, rr, rb, re);
+            if (rb >= re) continue;
+            const uint64_t rbase = rr * (uint64_t)nc;
+            if (inner) {
+                const uint64_t klo = rbase + (uint64_t)(cx - 1), khi = klo + 2;
+                for (int32_t c = lower_bound_u64(A.cell_key, rb, re, klo); c < re; c++) {
+                    const uint64_t nkey = A.cell_key[c];
+                    if (nkey > khi) break;
+                    if (nkey < cell) continue;
+                    link_cell<AUTOLINK>(A, a, s0, s1, oa, c, (int)(nkey - klo) - 1, dy, dz,
+                                        ra);
+                }
+            } else {
+                for (int dx = -1; dx <= 1; dx++) {
+                    int64_t nx = cx + dx;
+                    nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
+                    const uint64_t nkey = rbase + (uint64_t)nx;
+                    if (nkey < cell) continue;
+                    const int32_t c = lower_bound_u64(A.cell_key, rb, re, nkey);
+                    if (c < re && A.cell_key[c] == nkey)
+                        link_cell<AUTOLINK>(A, a, s0, s1, oa, c, dx, dy, dz, ra);
                 }
             }
         }
@@ -322,19 +347,15 @@ static int plan_grid(float L, float ll, Grid3* g) {
     return RS_OK;
 }
 
-static uint64_t pow2_at_least(uint64_t v) {
-    uint64_t p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
 int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
               int32_t* labels, int64_t* n_groups, hipStream_t st) {
     Grid3 g;
     RS_TRY(plan_grid(L, ll, &g));
     const int BT = 256;
     // footprint (upper bounds: octants and cells <= n)
-    uint64_t hcap = pow2_at_least((uint64_t)2 * (uint64_t)n + 64);
+    // dense row table when the grid has few rows for the particle count
+    const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
+    const bool row_table = rows <= std::max<uint64_t>(4 * (uint64_t)n, 1u << 20);
     size_t bytes = 0;
     auto add = [&](size_t b) { bytes += arena_round(b); };
     add(8 * n); add(8 * n);                 // keys in / out
@@ -344,7 +365,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(4 * (n + 1)); add(n + 1);           // octant start, bits
     add(4 * (n + 1)); add(8 * (n + 1));     // cell octant start, keys
     add(4 * n); add(4 * n);                 // parent, minidx
-    add(8 * hcap); add(4 * hcap);           // hash
+    if (row_table) add(4 * (rows + 1));      // row table
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
     Arena* ar;
@@ -366,8 +387,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     uint64_t* cell_key = take<uint64_t>(ar, n + 1);
     int32_t* parent = take<int32_t>(ar, n);
     int32_t* minidx = take<int32_t>(ar, n);
-    uint64_t* hk = take<uint64_t>(ar, hcap);
-    int32_t* hv = take<int32_t>(ar, hcap);
+    int32_t* row_start = row_table ? take<int32_t>(ar, rows + 1) : nullptr;
     size_t stb = sort_temp_bytes(n);
     void* stemp = arena_take(ar, stb);
     void* ctemp = arena_take(ar, scan_temp_bytes(n));
@@ -391,19 +411,20 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     if (hcnt[0]) return RS_ERANGE;
     int32_t n_oct = hcnt[1], n_cell = hcnt[2];
 
-    uint64_t mask = pow2_at_least((uint64_t)2 * (uint64_t)n_cell + 64) - 1;
-    RS_HIP(hipMemsetAsync(hk, 0xff, (mask + 1) * sizeof(uint64_t), st));
     k_tables<<<gb, BT, 0, st>>>(kout, n, oflag, oex, cflag, cex, oct_start, oct_bits, cell_oct,
                                 cell_key, parent, g.autolink);
     RS_HIP(hipGetLastError());
     // sentinels: oct_start[n_oct] = n, cell_oct[n_cell] = n_oct
     RS_TRY(fill_i32(oct_start + n_oct, (int32_t)n, 1, st));
     RS_TRY(fill_i32(cell_oct + n_cell, n_oct, 1, st));
-    k_hash_insert<<<grid_for(n_cell, BT, 1ll << 31), BT, 0, st>>>(cell_key, n_cell, hk, hv, mask);
+    if (row_table)
+        k_row_start<<<grid_for((int64_t)rows + 1, BT, 1ll << 31), BT, 0, st>>>(
+            cell_key, n_cell, g.nc, (int64_t)rows, row_start);
     k_parent_init<<<gb, BT, 0, st>>>(n, oflag, oex, oct_start, parent, g.autolink);
     RS_HIP(hipGetLastError());
 
-    LinkArgs A{oct_start, oct_bits, cell_oct, hk, hv, mask, kout, sx, sy, sz, parent, n_oct, g};
+    LinkArgs A{oct_start, oct_bits, cell_oct, cell_key, row_start, n_cell, kout, sx, sy, sz,
+               parent, n_oct, g};
     unsigned go = grid_for(n_oct, 256, 1ll << 31);
     prof_begin("fof3d_link", st);
     if (g.autolink)

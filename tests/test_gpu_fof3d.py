@@ -62,6 +62,22 @@ def test_small_box_few_cells():
         _check(pos, L, ll)
 
 
+def test_sparse_grid_rows_by_search():
+    # ~2000^2 cell rows for 20k particles: no dense row table, each row's
+    # cells are found by binary search over all cell keys; clumps straddle
+    # the periodic faces
+    rng = np.random.default_rng(6)
+    L, ll = 100.0, 0.05
+    centres = rng.random((150, 3)) * L
+    centres[:30, 0] = rng.choice([0.01, L - 0.01], 30)
+    centres[30:60, 2] = rng.choice([0.02, L - 0.02], 30)
+    pos = centres[rng.integers(0, 150, 18000)] + rng.normal(0, 0.04, (18000, 3))
+    pos = np.concatenate([pos, rng.random((2000, 3)) * L])
+    pos = np.mod(pos, L).astype(F32)
+    pos[pos >= L] = 0
+    _check(pos, L, ll)
+
+
 def test_edge_cases():
     # one particle; two at the threshold; all coincident; points on the faces
     _check(np.array([[1.0, 2.0, 3.0]], F32), 8.0, 0.2)
