@@ -13,6 +13,7 @@ namespace rs {
 
 constexpr int TSTACK = 520;   // >= 64 internal children x 8 levels
 constexpr int TLIST = 256;    // candidate leaves buffered before processing
+constexpr int THITS = 256;    // linked pairs buffered before their unions
 
 struct TileRec {
     float lo[6], hi[6];
@@ -74,13 +75,17 @@ RS_DEV float bcast(float v, int src) {
 }
 
 // Links within l among later members.  One wavefront per tile of 64
-// consecutive members of one node (tiles never straddle nodes).
+// consecutive members of one node (tiles never straddle nodes).  Pairs found
+// within l are queued in LDS and united 64 at a time, one pair per lane, so
+// that the union-find walks of many pairs are in flight together instead of
+// one or two lanes walking while the rest of the wavefront waits.
 template <bool O32>
 __global__ void __launch_bounds__(64)
 k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
             int32_t* __restrict__ par) {
     __shared__ TStackEnt stk[TSTACK];
     __shared__ int32_t list[TLIST];
+    __shared__ int2 hits[THITS];
     const int lane = threadIdx.x;
     const int t = xcd_chunk_index(blockIdx.x, chunk);
     if (t >= ntiles) return;
@@ -116,6 +121,14 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
     }
     const int64_t first_act = ts + __ffsll((unsigned long long)amask) - 1;
 
+    int nhit = 0;
+    auto unite_hits = [&]() {
+        __syncthreads();
+        for (int i = lane; i < nhit; i += 64) uf_unite(par, hits[i].x, hits[i].y);
+        nhit = 0;
+        __syncthreads();
+    };
+
     // one pass over the buffered candidate leaves: per leaf, the queries
     // whose own bound admits it are replayed against its members
     auto process = [&](int n) {
@@ -138,13 +151,20 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
                 const float bx = bcast(qx, src), by = bcast(qy, src), bz = bcast(qz, src);
                 const float bu = bcast(qu, src), bv = bcast(qv, src), bw = bcast(qw, src);
                 const int64_t mb = ts + src;
+                bool hit = false;
                 if (has && mj > mb) {
                     float dd = P.nowrap
                         ? phase_d2<false>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
                                           P.c, pp.L, pp.h)
                         : phase_d2<true>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
                                          P.c, pp.L, pp.h);
-                    if (dd <= l2) uf_unite(par, (int)mb, (int)mj);
+                    hit = dd <= l2;
+                }
+                const uint64_t hm = __ballot(hit);
+                if (hm) {
+                    if (nhit + __popcll(hm) > THITS) unite_hits();
+                    if (hit) hits[nhit + __popcll(hm & lanemask_lt())] = make_int2((int)mb, (int)mj);
+                    nhit += __popcll(hm);
                 }
             }
         }
@@ -187,6 +207,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
         }
     }
     process(nlist);
+    unite_hits();
 }
 
 int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {

@@ -416,6 +416,21 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                 const uint64_t imask = __ballot(need && !leaf);
                 if (need && !leaf)
                     stk[sp + __popcll(imask & lanemask_lt())] = StackEnt{r.cfirst, r.ccount, lb};
+                if (cull && __popcll(imask) > 1) {
+                    // the nearest internal child goes on top: visited first,
+                    // it lowers `best` soonest and prunes its siblings
+                    const float m = wmin_nonneg(need && !leaf ? lb : __builtin_huge_valf());
+                    const uint64_t w = __ballot(need && !leaf && lb == m);
+                    if (lane == __ffsll((unsigned long long)w) - 1) {
+                        const int pos = sp + __popcll(imask & lanemask_lt());
+                        const int top = sp + __popcll(imask) - 1;
+                        if (pos != top) {
+                            const StackEnt e = stk[top];
+                            stk[top] = stk[pos];
+                            stk[pos] = e;
+                        }
+                    }
+                }
                 sp += __popcll(imask);
                 __syncthreads();
                 uint64_t mk = __ballot(need && leaf);
@@ -466,6 +481,8 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                     bl = fminf(bl, fminf(fminf(d4[0], d4[1]), fminf(d4[2], d4[3])));
                     best = wmin_nonneg(bl);
                     if (best <= lo2) mk = 0;
+                    // leaves still queued that the lowered `best` excludes
+                    if (cull) mk &= __ballot(lb < best);
                 }
                 if (best <= lo2) {
                     sp = 0;
