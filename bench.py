@@ -178,7 +178,7 @@ def speedups(arrs, cfg, labels, model, ms_learned):
             "plain_ms_per_step": ms_p2, "learned_ms_per_step_c256": ms_l2}
 
 
-def cpu_baseline(arrs, cfg, target=1000000):
+def cpu_baseline(arrs, cfg, target=1600000):
     """The oracle (single-threaded C) on a cubic sub-box of the same data,
     run as a periodic box of its own: 3D FoF then the 6D hierarchy."""
     import oracle
