@@ -7,6 +7,8 @@
 // exact bound admits the leaf are replayed against it: each such query is
 // broadcast to the lanes, every lane evaluates the pair with its member.
 // Candidate data is read once per tile instead of once per query.
+#include <type_traits>
+
 #include "phase_common.h"
 
 namespace rs {
@@ -130,8 +132,11 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
     };
 
     // one pass over the buffered candidate leaves: per leaf, the queries
-    // whose own bound admits it are replayed against its members
-    auto process = [&](int n) {
+    // whose own bound admits it are replayed against its members.  The pair
+    // test runs on every lane (a lane past the leaf's end holds a valid
+    // member and is masked afterwards), so the replay has no divergent branch.
+    auto process = [&](int n, auto nowrap) {
+        constexpr bool NOWRAP = decltype(nowrap)::value;
         for (int li = 0; li < n; li++) {
             const TileRec r = trec_load(tb.erec, list[li]);
             bool need = act && r.end > mq + 1;
@@ -145,25 +150,25 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
                         zj = mload<O32>(T.z, mjj);
             const float uj = mload<O32>(T.vx, mjj), vj = mload<O32>(T.vy, mjj),
                         wj = mload<O32>(T.vz, mjj);
+            // pairs are taken with later members only: for query ts + src the
+            // lanes holding later members are those above src + ts - r.start
+            const uint64_t hasm = __builtin_amdgcn_ballot_w64(has);
+            const int32_t off = (int32_t)(ts + 1) - __builtin_amdgcn_readfirstlane(r.start);
             while (mk) {
                 const int src = __ffsll((unsigned long long)mk) - 1;
                 mk &= mk - 1;
                 const float bx = bcast(qx, src), by = bcast(qy, src), bz = bcast(qz, src);
                 const float bu = bcast(qu, src), bv = bcast(qv, src), bw = bcast(qw, src);
-                const int64_t mb = ts + src;
-                bool hit = false;
-                if (has && mj > mb) {
-                    float dd = P.nowrap
-                        ? phase_d2<false>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
-                                          P.c, pp.L, pp.h)
-                        : phase_d2<true>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj, wj, P.a,
-                                         P.c, pp.L, pp.h);
-                    hit = dd <= l2;
-                }
-                const uint64_t hm = __ballot(hit);
+                const float dd = phase_d2<!NOWRAP>(bx, by, bz, bu, bv, bw, xj, yj, zj, uj, vj,
+                                                   wj, P.a, P.c, pp.L, pp.h);
+                const int32_t k0 = off + src;
+                const uint64_t later = k0 <= 0 ? hasm : (k0 >= 64 ? 0ull : hasm & (~0ull << k0));
+                const uint64_t hm = later & __builtin_amdgcn_ballot_w64(dd <= l2);
                 if (hm) {
                     if (nhit + __popcll(hm) > THITS) unite_hits();
-                    if (hit) hits[nhit + __popcll(hm & lanemask_lt())] = make_int2((int)mb, (int)mj);
+                    if ((hm >> lane) & 1)
+                        hits[nhit + __popcll(hm & lanemask_lt())] =
+                            make_int2((int)(ts + src), (int)mj);
                     nhit += __popcll(hm);
                 }
             }
@@ -198,7 +203,8 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
             const uint64_t lmask = __ballot(need && leaf);
             if (nlist + __popcll(lmask) > TLIST) {
                 __syncthreads();
-                process(nlist);
+                if (P.nowrap) process(nlist, std::true_type{});
+                else process(nlist, std::false_type{});
                 nlist = 0;
             }
             if (need && leaf) list[nlist + __popcll(lmask & lanemask_lt())] = k;
@@ -206,7 +212,8 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
             __syncthreads();
         }
     }
-    process(nlist);
+    if (P.nowrap) process(nlist, std::true_type{});
+    else process(nlist, std::false_type{});
     unite_hits();
 }
 

@@ -395,15 +395,34 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
         __syncthreads();
         while (sp > 0) {
             sp--;
-            const StackEnt se = stk[sp];
+            StackEnt se = stk[sp];
+            // most cells have at most 32 children: the next entry, when it is
+            // as small and still needed, is visited in the same pass on the
+            // upper half of the lanes (the live entries of each depth still
+            // come from one pass, at most 64, so the stack bound holds)
+            StackEnt se2{0, 0, 0.0f};
+            if (se.ccount <= 32 && sp > 0) {
+                const StackEnt t2 = stk[sp - 1];
+                if (t2.ccount <= 32 && (!cull || t2.lb < best)) {
+                    se2 = t2;
+                    sp--;
+                }
+            }
             __syncthreads();
-            if (cull && !(se.lb < best)) continue;
-            for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
-                const int32_t k = se.cfirst + b0 + lane;
+            const bool pair = se2.ccount > 0;
+            if (cull && !(se.lb < best)) {
+                if (!pair) continue;
+                se.ccount = 0;
+            }
+            for (int32_t b0 = 0; b0 < se.ccount || (pair && b0 == 0); b0 += 64) {
+                const bool hi_half = pair && lane >= 32;
+                const int32_t k = hi_half ? se2.cfirst + lane - 32 : se.cfirst + b0 + lane;
+                const bool valid = hi_half ? lane - 32 < se2.ccount
+                                           : b0 + lane < se.ccount && (!pair || lane < 32);
                 Rec r;
                 bool need = false;
                 float lb = 0.0f;
-                if (b0 + lane < se.ccount && k != e0) {
+                if (valid && k != e0) {
                     r = rec_load(tb.erec, k);
                     lb = cull ? rec_lb(r, q, P.a, P.c, A.slack) : 0.0f;
                     need = lb < best;
