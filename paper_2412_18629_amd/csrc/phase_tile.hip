@@ -181,11 +181,37 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
     int sp = 1;
     __syncthreads();
     while (sp > 0) {
+        // cells average about ten children: up to four entries whose
+        // children fit in 64 lanes are scanned in one pass, each on its own
+        // run of lanes (a pass pushes at most 64 entries, as one cell does)
         sp--;
-        const TStackEnt se = stk[sp];
+        TStackEnt se = stk[sp];
+        int32_t cf1 = 0, cf2 = 0, cf3 = 0, e1 = 64, e2 = 64, e3 = 64, tot = se.ccount;
+        if (tot <= 64) {
+            if (sp > 0 && tot + stk[sp - 1].ccount <= 64) {
+                cf1 = stk[--sp].cfirst;
+                e1 = tot;
+                tot += stk[sp].ccount;
+                if (sp > 0 && tot + stk[sp - 1].ccount <= 64) {
+                    cf2 = stk[--sp].cfirst;
+                    e2 = tot;
+                    tot += stk[sp].ccount;
+                    if (sp > 0 && tot + stk[sp - 1].ccount <= 64) {
+                        cf3 = stk[--sp].cfirst;
+                        e3 = tot;
+                        tot += stk[sp].ccount;
+                    }
+                }
+            }
+            // lanes [0, e1) scan the first entry, [e1, e2) the second, ...
+            se.ccount = tot;
+        }
         __syncthreads();
         for (int32_t b0 = 0; b0 < se.ccount; b0 += 64) {
-            const int32_t k = se.cfirst + b0 + lane;
+            const int32_t k = lane >= e3   ? cf3 + lane - e3
+                              : lane >= e2 ? cf2 + lane - e2
+                              : lane >= e1 ? cf1 + lane - e1
+                                           : se.cfirst + b0 + lane;
             bool need = false, leaf = false;
             TileRec r;
             r.cfirst = -1;
