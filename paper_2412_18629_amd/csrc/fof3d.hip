@@ -308,19 +308,31 @@ __global__ void k_min_index(int64_t n, const int32_t* __restrict__ parent,
     }
 }
 
-__global__ void k_write_labels(int64_t n, const int32_t* __restrict__ parent,
-                               const int32_t* __restrict__ perm,
-                               const int32_t* __restrict__ minidx, int32_t* __restrict__ labels,
-                               unsigned long long* __restrict__ nroots) {
-    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool root = false;
-    if (s < n) {
-        int32_t r = parent[s];
+// labels in the caller's order; roots counted per thread over a grid-stride
+// loop and reduced per block, so the group counter takes one atomic per
+// block rather than one per wavefront
+constexpr int WL_BLOCKS = 4096;
+
+__global__ void __launch_bounds__(256)
+k_write_labels(int64_t n, const int32_t* __restrict__ parent, const int32_t* __restrict__ perm,
+               const int32_t* __restrict__ minidx, int32_t* __restrict__ labels,
+               unsigned long long* __restrict__ nroots) {
+    __shared__ unsigned long long part[4];
+    unsigned long long mine = 0;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = parent[s];
         labels[perm[s]] = minidx[r];
-        root = (r == (int32_t)s);
+        mine += r == (int32_t)s;
     }
-    unsigned long long b = __ballot(root);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nroots, (unsigned long long)__popcll(b));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mine += (unsigned long long)__shfl_xor((long long)mine, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = part[0] + part[1] + part[2] + part[3];
+        if (b) atomicAdd(nroots, b);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -438,7 +450,8 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     RS_TRY(fill_i32(minidx, 0x7fffffff, n, st));
     k_min_index<<<gb, BT, 0, st>>>(n, parent, perm, minidx);
     unsigned long long* nroots = reinterpret_cast<unsigned long long*>(cnt + 4);
-    k_write_labels<<<gb, BT, 0, st>>>(n, parent, perm, minidx, labels, nroots);
+    k_write_labels<<<grid_for(n, 256, WL_BLOCKS), 256, 0, st>>>(n, parent, perm, minidx, labels,
+                                                               nroots);
     RS_HIP(hipGetLastError());
     unsigned long long* hroots = reinterpret_cast<unsigned long long*>(hcnt + 4);
     RS_HIP(hipMemcpyAsync(hroots, nroots, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));

@@ -33,67 +33,69 @@ RS_DEV int32_t morton_lower_bound(const uint64_t* __restrict__ keys, int32_t lo,
     return lo;
 }
 
-// One wavefront (one block) per internal node of `level`: find its children
-// by lane-parallel binary search (lane d -> digit d), pack the small ones into
-// leaves, allocate entries and child internal nodes.
-__global__ void __launch_bounds__(64)
-k_tree_split(const uint64_t* __restrict__ keys, int32_t node_begin, int level, TreeBuf tb) {
-    const int lane = threadIdx.x;
-    const int32_t x = node_begin + blockIdx.x;
-    const int32_t start = tb.istart[x], end = tb.iend[x];
+// One wavefront per internal node of `level`, four per block: find its
+// children by lane-parallel binary search (lane d -> digit d), pack the
+// small ones into leaves, allocate entries and child internal nodes.  The
+// inode and entry counters are adjacent, so one 64-bit atomic per block
+// reserves both for its four nodes (one counter hit by every node was the
+// cost of this kernel).
+constexpr int SPLIT_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * SPLIT_WAVES)
+k_tree_split(const uint64_t* __restrict__ keys, int32_t node_begin, int32_t node_end, int level,
+             TreeBuf tb) {
+    __shared__ unsigned long long req[SPLIT_WAVES];
+    __shared__ unsigned long long sbase;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t x = node_begin + blockIdx.x * SPLIT_WAVES + w;
+    const bool valid = x < node_end;
+    const int32_t start = valid ? tb.istart[x] : 0, end = valid ? tb.iend[x] : 0;
     const int32_t cnt_all = end - start;
-    if (level >= TREE_LEVELS) {
+    const bool finest = level >= TREE_LEVELS;
+    int32_t n_int = 0, n_ent = 0, lo = 0, cnt = 0;
+    if (finest) {
         // finest cell: cut into 64-member leaves
-        const int32_t nch = (cnt_all + 63) / 64;
-        int32_t base = 0;
-        if (lane == 0) base = atomicAdd(tb.n_entry, nch);
-        base = __shfl(base, 0, 64);
-        const bool ok = base + nch <= tb.cap_entry;
-        for (int32_t k = lane; k < nch && ok; k += 64) {
-            int32_t e = base + k;
-            tb.estart[e] = start + 64 * k;
-            tb.eend[e] = min(start + 64 * (k + 1), end);
-            tb.enode[e] = -1;
+        n_ent = (cnt_all + 63) / 64;
+    } else if (valid) {
+        const int shift = 42 - 6 * (level + 1);
+        const uint64_t prefix = (keys[start] & MORTON_MASK) >> (shift + 6);
+        const uint64_t target = ((prefix << 6) | (uint64_t)lane) << shift;
+        lo = morton_lower_bound(keys, start, end, target);
+        int32_t hi = __shfl_down(lo, 1, 64);
+        if (lane == 63) hi = end;
+        cnt = hi - lo;
+        // every lane runs the packing walk over the 64 digits (values
+        // broadcast by shuffles), so all counts agree
+        int32_t run = 0;
+        for (int d = 0; d < 64; d++) {
+            const int32_t c = __shfl(cnt, d, 64);
+            if (c == 0) continue;
+            if (c > 64) {
+                if (run) { n_ent++; run = 0; }
+                n_int++;
+                n_ent++;
+            } else if (run + c > 64) {
+                n_ent++;
+                run = c;
+            } else {
+                run += c;
+            }
         }
-        if (lane == 0) {
-            if (!ok) atomicOr(tb.overflow, 1);
-            tb.cfirst[x] = ok ? base : 0;
-            tb.ccount[x] = ok ? nch : 0;
-        }
-        return;
+        if (run) n_ent++;
     }
-    const int shift = 42 - 6 * (level + 1);
-    const uint64_t prefix = (keys[start] & MORTON_MASK) >> (shift + 6);
-    const uint64_t target = ((prefix << 6) | (uint64_t)lane) << shift;
-    const int32_t lo = morton_lower_bound(keys, start, end, target);
-    int32_t hi = __shfl_down(lo, 1, 64);
-    if (lane == 63) hi = end;
-    const int32_t cnt = hi - lo;
-    // every lane runs the packing walk over the 64 digits (values broadcast
-    // by shuffles), so all counts agree; lane 0 writes
-    int32_t n_int = 0, n_ent = 0, run = 0;
-    for (int d = 0; d < 64; d++) {
-        const int32_t c = __shfl(cnt, d, 64);
-        if (c == 0) continue;
-        if (c > 64) {
-            if (run) { n_ent++; run = 0; }
-            n_int++;
-            n_ent++;
-        } else if (run + c > 64) {
-            n_ent++;
-            run = c;
-        } else {
-            run += c;
-        }
+    if (lane == 0) req[w] = ((unsigned long long)n_ent << 32) | (unsigned long long)n_int;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < SPLIT_WAVES; k++) tot += req[k];
+        // low word: n_inode, high word: n_entry
+        sbase = atomicAdd(reinterpret_cast<unsigned long long*>(tb.n_inode), tot);
     }
-    if (run) n_ent++;
-    int32_t ebase = 0, ibase = 0;
-    if (lane == 0) {
-        ebase = atomicAdd(tb.n_entry, n_ent);
-        ibase = atomicAdd(tb.n_inode, n_int);
-    }
-    ebase = __shfl(ebase, 0, 64);
-    ibase = __shfl(ibase, 0, 64);
+    __syncthreads();
+    if (!valid) return;
+    unsigned long long bw = sbase;
+    for (int k = 0; k < w; k++) bw += req[k];
+    const int32_t ibase = (int32_t)(bw & 0xffffffffull), ebase = (int32_t)(bw >> 32);
     const bool ok = ebase + n_ent <= tb.cap_entry && ibase + n_int <= tb.cap_inode;
     if (lane == 0) {
         if (!ok) atomicOr(tb.overflow, 1);
@@ -101,8 +103,16 @@ k_tree_split(const uint64_t* __restrict__ keys, int32_t node_begin, int level, T
         tb.ccount[x] = ok ? n_ent : 0;
     }
     if (!ok) return;
-    int32_t e = ebase, in = ibase, rs0 = -1, re0 = -1;
-    run = 0;
+    if (finest) {
+        for (int32_t k = lane; k < n_ent; k += 64) {
+            const int32_t e = ebase + k;
+            tb.estart[e] = start + 64 * k;
+            tb.eend[e] = min(start + 64 * (k + 1), end);
+            tb.enode[e] = -1;
+        }
+        return;
+    }
+    int32_t e = ebase, in = ibase, rs0 = -1, re0 = -1, run = 0;
     for (int d = 0; d < 64; d++) {
         const int32_t c = __shfl(cnt, d, 64);
         const int32_t l0 = __shfl(lo, d, 64);
@@ -549,7 +559,8 @@ int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* n
     for (int level = 0; level <= TREE_LEVELS; level++) {
         level_begin->push_back(b);
         if (e > b) {
-            k_tree_split<<<e - b, 64, 0, st>>>(skeys, b, level, tb);
+            k_tree_split<<<(e - b + SPLIT_WAVES - 1) / SPLIT_WAVES, 64 * SPLIT_WAVES, 0, st>>>(
+                skeys, b, e, level, tb);
             RS_HIP(hipGetLastError());
         }
         RS_HIP(hipMemcpyAsync(hc, tb.n_inode, sizeof(int32_t), hipMemcpyDeviceToHost, st));
