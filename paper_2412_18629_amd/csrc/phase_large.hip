@@ -564,8 +564,16 @@ k_lcount(const LItem* __restrict__ items, const float* __restrict__ d2,
         a += d == 0.0f;
         b += d < __builtin_huge_valf();
     }
-    atomicAdd(c, a);
-    atomicAdd(c + 1, b);
+    // wavefront sums first: one LDS atomic per wavefront, not per thread
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(c, a);
+        atomicAdd(c + 1, b);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(lcnt + 2 * it.v, c[0]);
