@@ -54,10 +54,19 @@ RS_DEV float metric(float a, float Dx, float c, float Dv) {
 // Invariant: parent[v] <= v, roots satisfy parent[r] == r.  Hooks always put
 // the larger root under the smaller one (CAS on the root), so no cycle can
 // form; path halving stores only ancestors, which is benign under races.
+//
+// Reads are relaxed at workgroup scope, so they are served by the XCD's own
+// L2 and may return an older value written from another XCD.  An older value
+// of parent[v] is still an ancestor of v (links are never undone and every
+// store writes an ancestor), so a walk still ends at a former root, two walks
+// ending at the same node still prove one component, and a stale answer only
+// costs a redundant test.  Hooking is a CAS at agent scope on the root itself:
+// it fails on a stale root and returns the current parent, which is smaller,
+// so the retry loop makes progress.  Path-halving stores stay at agent scope.
 // ---------------------------------------------------------------------------
 
 RS_DEV int uf_load(const int* p, int v) {
-    return __hip_atomic_load(p + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 RS_DEV int uf_find(int* par, int v) {

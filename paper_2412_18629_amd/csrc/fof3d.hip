@@ -96,8 +96,7 @@ __global__ void k_tables(const uint64_t* __restrict__ keys, int64_t n,
                          const int32_t* __restrict__ oflag, const int32_t* __restrict__ oex,
                          const int32_t* __restrict__ cflag, const int32_t* __restrict__ cex,
                          int32_t* __restrict__ oct_start, uint8_t* __restrict__ oct_bits,
-                         int32_t* __restrict__ cell_oct, uint64_t* __restrict__ cell_key,
-                         int32_t* __restrict__ parent, bool autolink) {
+                         int32_t* __restrict__ cell_oct, uint64_t* __restrict__ cell_key) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     if (oflag[s]) {
@@ -112,19 +111,9 @@ __global__ void k_tables(const uint64_t* __restrict__ keys, int64_t n,
     }
 }
 
-// parent[s] = first slot of s's octant (auto-link) or s
-__global__ void k_parent_init(int64_t n, const int32_t* __restrict__ oflag,
-                              const int32_t* __restrict__ oex,
-                              const int32_t* __restrict__ oct_start,
-                              int32_t* __restrict__ parent, bool autolink) {
+__global__ void k_iota(int64_t n, int32_t* __restrict__ v) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    if (!autolink) {
-        parent[s] = (int32_t)s;
-        return;
-    }
-    int32_t o = oex[s] + oflag[s] - 1;   // octant index of slot s
-    parent[s] = oct_start[o];
+    if (s < n) v[s] = (int32_t)s;
 }
 
 // first index in [b, e) whose key is >= k (keys ascending)
@@ -155,7 +144,7 @@ struct LinkArgs {
     int32_t n_cell;
     const uint64_t* keys;       // sorted keys
     const float *sx, *sy, *sz;  // sorted positions
-    int32_t* parent;
+    int32_t* parent;            // union-find over octants (auto-link) or over slots
     int32_t n_oct;
     Grid3 g;
 };
@@ -174,8 +163,10 @@ RS_DEV void row_cells(const LinkArgs& A, uint64_t rr, int32_t& b, int32_t& e) {
 
 // test octant a (slots [s0, s1), octant bits oa) against every later octant
 // of cell c, which sits at offset (dx, dy, dz) cells from a's cell
-// `ra` is a member of a's component (its last known root): finding from it
-// is a short walk, and it is updated to the current root on every use
+// `ra` is an element of a's component (its last known root): finding from it
+// is a short walk, and it is updated to the current root on every use.  With
+// auto-link the union-find runs over octant indices (one element per octant,
+// a dense array half the size of the slot array); otherwise over slots.
 template <bool AUTOLINK>
 RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int oa, int32_t c,
                       int dx, int dy, int dz, int32_t& ra) {
@@ -190,11 +181,12 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             if (ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 || ddz == -3)
                 continue;
         }
-        const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
         if (AUTOLINK) {
+            // every octant is one element: its members are linked already
             ra = uf_find(A.parent, ra);
-            const int32_t rb = uf_find(A.parent, t0);
+            const int32_t rb = uf_find(A.parent, b);
             if (ra == rb) continue;
+            const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
             bool hit = false;
             for (int32_t i = s0; i < s1 && !hit; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
@@ -207,6 +199,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             }
             if (hit) uf_unite(A.parent, ra, rb);
         } else {
+            const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
             for (int32_t i = s0; i < s1; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
                 for (int32_t j = t0; j < t1; j++)
@@ -243,7 +236,7 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
                     uf_unite(A.parent, i, j);
         }
     }
-    int32_t ra = s0;
+    int32_t ra = AUTOLINK ? a : s0;
     // x - 1 .. x + 1 are one contiguous key range unless x wraps
     const bool inner = nc >= 3 && cx >= 1 && cx <= nc - 2;
     for (int dz = -1; dz <= 1; dz++) {
@@ -280,6 +273,19 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
             }
         }
     }
+}
+
+
+// slot parents from the flattened octant roots: each slot points at the
+// first slot of its component's root octant (one slot per component is its
+// own parent, as with the slot-level union-find)
+__global__ void k_oct2slot(int64_t n, const int32_t* __restrict__ oflag,
+                           const int32_t* __restrict__ oex, const int32_t* __restrict__ oct_start,
+                           const int32_t* __restrict__ poct, int32_t* __restrict__ parent) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t o = oex[s] + oflag[s] - 1;
+    parent[s] = oct_start[poct[o]];
 }
 
 __global__ void k_flatten(int64_t n, int32_t* __restrict__ parent) {
@@ -377,6 +383,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(4 * (n + 1)); add(n + 1);           // octant start, bits
     add(4 * (n + 1)); add(8 * (n + 1));     // cell octant start, keys
     add(4 * n); add(4 * n);                 // parent, minidx
+    add(4 * (n + 1));                       // octant union-find
     if (row_table) add(4 * (rows + 1));      // row table
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
@@ -399,6 +406,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     uint64_t* cell_key = take<uint64_t>(ar, n + 1);
     int32_t* parent = take<int32_t>(ar, n);
     int32_t* minidx = take<int32_t>(ar, n);
+    int32_t* poct = take<int32_t>(ar, n + 1);
     int32_t* row_start = row_table ? take<int32_t>(ar, rows + 1) : nullptr;
     size_t stb = sort_temp_bytes(n);
     void* stemp = arena_take(ar, stb);
@@ -424,7 +432,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     int32_t n_oct = hcnt[1], n_cell = hcnt[2];
 
     k_tables<<<gb, BT, 0, st>>>(kout, n, oflag, oex, cflag, cex, oct_start, oct_bits, cell_oct,
-                                cell_key, parent, g.autolink);
+                                cell_key);
     RS_HIP(hipGetLastError());
     // sentinels: oct_start[n_oct] = n, cell_oct[n_cell] = n_oct
     RS_TRY(fill_i32(oct_start + n_oct, (int32_t)n, 1, st));
@@ -432,12 +440,16 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     if (row_table)
         k_row_start<<<grid_for((int64_t)rows + 1, BT, 1ll << 31), BT, 0, st>>>(
             cell_key, n_cell, g.nc, (int64_t)rows, row_start);
-    k_parent_init<<<gb, BT, 0, st>>>(n, oflag, oex, oct_start, parent, g.autolink);
+    unsigned go = grid_for(n_oct, 256, 1ll << 31);
+    if (g.autolink) {
+        k_iota<<<go, 256, 0, st>>>(n_oct, poct);
+    } else {
+        k_iota<<<gb, BT, 0, st>>>(n, parent);
+    }
     RS_HIP(hipGetLastError());
 
     LinkArgs A{oct_start, oct_bits, cell_oct, cell_key, row_start, n_cell, kout, sx, sy, sz,
-               parent, n_oct, g};
-    unsigned go = grid_for(n_oct, 256, 1ll << 31);
+               g.autolink ? poct : parent, n_oct, g};
     prof_begin("fof3d_link", st);
     if (g.autolink)
         k_link<true><<<go, 256, 0, st>>>(A);
@@ -446,7 +458,12 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     RS_HIP(hipGetLastError());
     prof_end("fof3d_link", st, (double)n);
 
-    k_flatten<<<gb, BT, 0, st>>>(n, parent);
+    if (g.autolink) {
+        k_flatten<<<go, 256, 0, st>>>(n_oct, poct);
+        k_oct2slot<<<gb, BT, 0, st>>>(n, oflag, oex, oct_start, poct, parent);
+    } else {
+        k_flatten<<<gb, BT, 0, st>>>(n, parent);
+    }
     RS_TRY(fill_i32(minidx, 0x7fffffff, n, st));
     k_min_index<<<gb, BT, 0, st>>>(n, parent, perm, minidx);
     unsigned long long* nroots = reinterpret_cast<unsigned long long*>(cnt + 4);
