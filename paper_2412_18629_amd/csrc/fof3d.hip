@@ -147,7 +147,16 @@ struct LinkArgs {
     int32_t* parent;            // union-find over octants (auto-link) or over slots
     int32_t n_oct;
     Grid3 g;
+    int2* heavy;                // deferred octant pairs (auto-link) ...
+    int32_t* n_heavy;           // ... their count (may exceed the capacity)
+    int32_t cap_heavy;
 };
+
+// octant pairs with more member pairs than this are deferred to a second
+// pass, run one wavefront per pair once every lighter pair has been linked:
+// by then most of them already share a root, and the rest are searched 64
+// member pairs at a time instead of serially by one thread
+constexpr int64_t HEAVY_PAIRS = 1024;
 
 // cells of row rr (cell indices [b, e))
 RS_DEV void row_cells(const LinkArgs& A, uint64_t rr, int32_t& b, int32_t& e) {
@@ -187,6 +196,13 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             const int32_t rb = uf_find(A.parent, b);
             if (ra == rb) continue;
             const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
+            if ((int64_t)(s1 - s0) * (t1 - t0) > HEAVY_PAIRS) {
+                const int32_t q = atomicAdd(A.n_heavy, 1);
+                if (q < A.cap_heavy) {
+                    A.heavy[q] = make_int2(a, b);
+                    continue;
+                }
+            }
             bool hit = false;
             for (int32_t i = s0; i < s1 && !hit; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
@@ -279,6 +295,35 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
 // slot parents from the flattened octant roots: each slot points at the
 // first slot of its component's root octant (one slot per component is its
 // own parent, as with the slot-level union-find)
+// the deferred octant pairs, one wavefront per pair (grid-stride): skipped
+// when already in one component, otherwise the member pairs are tested 64
+// at a time until the first one within ll
+constexpr int HEAVY_BLOCKS = 8192;
+
+__global__ void __launch_bounds__(64) k_link_heavy(LinkArgs A) {
+    const int lane = threadIdx.x;
+    const int32_t nq = min(*A.n_heavy, A.cap_heavy);
+    const Grid3& g = A.g;
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int2 pr = A.heavy[q];
+        const int32_t ra = uf_find(A.parent, pr.x), rb = uf_find(A.parent, pr.y);
+        if (__builtin_amdgcn_readfirstlane(ra) == __builtin_amdgcn_readfirstlane(rb)) continue;
+        const int32_t s0 = A.oct_start[pr.x], s1 = A.oct_start[pr.x + 1];
+        const int32_t t0 = A.oct_start[pr.y], t1 = A.oct_start[pr.y + 1];
+        bool hit = false;
+        for (int32_t i = s0; i < s1 && !hit; i++) {
+            const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+            for (int32_t j0 = t0; j0 < t1 && !hit; j0 += 64) {
+                const int32_t j = j0 + lane;
+                const bool near = j < t1 && pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j],
+                                                        g.L, g.h) <= g.ll2;
+                hit = __ballot(near) != 0;
+            }
+        }
+        if (hit && lane == 0) uf_unite(A.parent, ra, rb);
+    }
+}
+
 __global__ void k_oct2slot(int64_t n, const int32_t* __restrict__ oflag,
                            const int32_t* __restrict__ oex, const int32_t* __restrict__ oct_start,
                            const int32_t* __restrict__ poct, int32_t* __restrict__ parent) {
@@ -384,6 +429,8 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(4 * (n + 1)); add(8 * (n + 1));     // cell octant start, keys
     add(4 * n); add(4 * n);                 // parent, minidx
     add(4 * (n + 1));                       // octant union-find
+    const int64_t cap_heavy = n / 4 + 1024;
+    add(8 * cap_heavy); add(64);            // deferred octant pairs, count
     if (row_table) add(4 * (rows + 1));      // row table
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
@@ -407,6 +454,8 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     int32_t* parent = take<int32_t>(ar, n);
     int32_t* minidx = take<int32_t>(ar, n);
     int32_t* poct = take<int32_t>(ar, n + 1);
+    int2* heavy = take<int2>(ar, cap_heavy);
+    int32_t* n_heavy = take<int32_t>(ar, 16);
     int32_t* row_start = row_table ? take<int32_t>(ar, rows + 1) : nullptr;
     size_t stb = sort_temp_bytes(n);
     void* stemp = arena_take(ar, stb);
@@ -449,12 +498,16 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     RS_HIP(hipGetLastError());
 
     LinkArgs A{oct_start, oct_bits, cell_oct, cell_key, row_start, n_cell, kout, sx, sy, sz,
-               g.autolink ? poct : parent, n_oct, g};
+               g.autolink ? poct : parent, n_oct, g, heavy, n_heavy,
+               (int32_t)std::min<int64_t>(cap_heavy, INT32_MAX)};
     prof_begin("fof3d_link", st);
-    if (g.autolink)
+    if (g.autolink) {
+        RS_TRY(fill_i32(n_heavy, 0, 1, st));
         k_link<true><<<go, 256, 0, st>>>(A);
-    else
+        k_link_heavy<<<HEAVY_BLOCKS, 64, 0, st>>>(A);
+    } else {
         k_link<false><<<go, 256, 0, st>>>(A);
+    }
     RS_HIP(hipGetLastError());
     prof_end("fof3d_link", st, (double)n);
 
