@@ -33,13 +33,13 @@ RS_DEV int32_t morton_lower_bound(const uint64_t* __restrict__ keys, int32_t lo,
     return lo;
 }
 
-// One wavefront per internal node of `level`, sixteen per block: find its
+// One wavefront per internal node of `level`, four per block: find its
 // children by lane-parallel binary search (lane d -> digit d), pack the
 // small ones into leaves, allocate entries and child internal nodes.  The
 // inode and entry counters are adjacent, so one 64-bit atomic per block
-// reserves both for its sixteen nodes (one counter hit by every node was the
+// reserves both for its four nodes (one counter hit by every node was the
 // cost of this kernel).
-constexpr int SPLIT_WAVES = 16;
+constexpr int SPLIT_WAVES = 4;
 
 __global__ void __launch_bounds__(64 * SPLIT_WAVES)
 k_tree_split(const uint64_t* __restrict__ keys, int32_t node_begin, int32_t node_end, int level,
