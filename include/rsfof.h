@@ -110,6 +110,12 @@ typedef struct rs_tree {
                             were completed by the exact refinement */
     int64_t n_levels;    /* number of levels (max level + 1), 0 if no nodes */
     float* features;     /* [n_nodes * RS_NFEAT] with RS_FEATURES, else NULL */
+    int32_t* wide;       /* [n_nodes] 1 when the node's 3D group percolates: on some
+                            axis its members' integer displacements from the group's
+                            smallest-index member (nearest periodic image, as for the
+                            dispersions) span at least half the box, so the group's
+                            nearest-image frame, and with it every node of its
+                            hierarchy, is not translation invariant; else 0 */
 } rs_tree;
 
 /*

@@ -44,7 +44,7 @@ def _load():
     lib.oracle_fof3d.argtypes = [P, P, P, i64, f32, f32, P]
     lib.oracle_fof3d_brute.argtypes = [P, P, P, i64, f32, f32, P]
     lib.oracle_phase_fof.argtypes = [P, P, P, P, P, P, i64, f32, P, i32, i32, f64, i64,
-                                     i64, P, P, P, P, P, P, P, P, P, P, P]
+                                     i64, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_i128_to_f64.argtypes = [i64, ctypes.c_uint64]
     lib.oracle_i128_to_f64.restype = f64
     lib.oracle_select_rank.argtypes = [i64, f64]
@@ -80,7 +80,7 @@ def fof3d(x, y, z, box, link_len, brute=False):
     return lab
 
 
-NODE_FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2")
+NODE_FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide")
 
 
 def phase_fof(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=0.7,
@@ -97,7 +97,7 @@ def phase_fof(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=
                    parent=np.empty(cap, np.int32), size=np.empty(cap, np.int32),
                    l2=np.empty(cap, np.float32), a=np.empty(cap, np.float32),
                    c=np.empty(cap, np.float32), sx2=np.empty(cap, np.float32),
-                   sv2=np.empty(cap, np.float32))
+                   sv2=np.empty(cap, np.float32), wide=np.empty(cap, np.int32))
         deepest = np.empty(n, np.int32)
         nn = ctypes.c_int64(0)
         rc = lib.oracle_phase_fof(*[_ptr(a) for a in arrs], n, float(box), _ptr(lab),

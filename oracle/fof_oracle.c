@@ -482,7 +482,35 @@ typedef struct {
     int32_t level;
     int64_t parent;      /* creation index of the parent, -1 for level 0 */
     float l2, a, c, sx2, sv2;
+    int32_t wide;        /* the node's 3D group percolates (see group_wide) */
 } node_t;
+
+/*
+ * Percolation flag of a 3D group (SURVEY reading C13): on some axis the
+ * members' integer displacements from the reference member, brought to the
+ * nearest periodic image exactly as for the dispersions, span at least half
+ * the box (2 * (max - min) >= L_Q).  The nearest-image frame of such a group
+ * is not unique, so its dispersions, and through them every node of its
+ * hierarchy, are not invariant under translation; the children inherit it.
+ */
+static int32_t group_wide(const parts_t *p, const int64_t *mem, int64_t n, int64_t ref)
+{
+    const float *pc[3] = { p->x, p->y, p->z };
+    int64_t LQ = (int64_t)rint((double)p->L * 1048576.0);
+    for (int ax = 0; ax < 3; ax++) {
+        int64_t qref = (int64_t)rint((double)pc[ax][ref] * 1048576.0);
+        int64_t lo = 0, hi = 0;
+        for (int64_t m = 0; m < n; m++) {
+            int64_t d = (int64_t)rint((double)pc[ax][mem[m]] * 1048576.0) - qref;
+            if (2 * d > LQ) d -= LQ;
+            else if (2 * d <= -LQ) d += LQ;
+            if (d < lo) lo = d;
+            if (d > hi) hi = d;
+        }
+        if (2 * (hi - lo) >= LQ) return 1;
+    }
+    return 0;
+}
 
 typedef struct {
     node_t *v;
@@ -584,6 +612,7 @@ static int split_node(nodevec *nv, int64_t id, const parts_t *p, int32_t min_sub
         ch.n = count[r];
         ch.level = nd.level + 1;
         ch.parent = id;
+        ch.wide = nd.wide;
         ch.mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)ch.n);
         int64_t w = 0;
         for (int64_t i = r; i < n; i++)
@@ -606,8 +635,8 @@ static int cmp_nkey(const void *pa, const void *pb)
  * Full hierarchy.  Outputs (caller-allocated, capacity cap), canonical order
  * sorted by (level, smallest member index):
  *   level, min_index, parent (canonical index, -1 at level 0), size,
- *   l2, a, c, sx2, sv2 per node; deepest[n] = canonical index of the deepest
- *   node containing each particle, or -1.
+ *   l2, a, c, sx2, sv2, wide per node; deepest[n] = canonical index of the
+ *   deepest node containing each particle, or -1.
  * Returns 0, -1 bad argument, -2 range, -3 memory, -4 capacity (n_nodes is
  * still written so the caller can retry).
  */
@@ -617,7 +646,7 @@ int oracle_phase_fof(const float *x, const float *y, const float *z,
                      int32_t min_group, int32_t min_sub, double f, int64_t brute_max,
                      int64_t cap, int32_t *level, int32_t *min_index, int32_t *parent,
                      int32_t *size, float *l2, float *fa, float *fc, float *sx2, float *sv2,
-                     int32_t *deepest, int64_t *n_nodes)
+                     int32_t *wide, int32_t *deepest, int64_t *n_nodes)
 {
     if (n < 0 || !(L > 0.0f) || min_group < 2 || min_sub < 2 || !(f > 0.0 && f <= 1.0))
         return -1;
@@ -653,6 +682,8 @@ int oracle_phase_fof(const float *x, const float *y, const float *z,
     free(cnt); free(slot);
 
     for (int64_t id = 0; id < nv.n && rc == 0; id++)
+        nv.v[id].wide = group_wide(&p, nv.v[id].mem, nv.v[id].n, nv.v[id].mem[0]);
+    for (int64_t id = 0; id < nv.n && rc == 0; id++)
         rc = split_node(&nv, id, &p, min_sub, f, brute_max);
 
     *n_nodes = nv.n;
@@ -675,6 +706,7 @@ int oracle_phase_fof(const float *x, const float *y, const float *z,
             size[r] = (int32_t)nd->n;
             l2[r] = nd->l2; fa[r] = nd->a; fc[r] = nd->c;
             sx2[r] = nd->sx2; sv2[r] = nd->sv2;
+            wide[r] = nd->wide;
             for (int64_t m = 0; m < nd->n; m++) deepest[nd->mem[m]] = (int32_t)r;
         }
         free(ord); free(canon);

@@ -42,7 +42,7 @@ class _Tree(ctypes.Structure):
                 ("sx2", ctypes.c_void_p), ("sv2", ctypes.c_void_p),
                 ("deepest", ctypes.c_void_p), ("n_accepted", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int64), ("n_levels", ctypes.c_int64),
-                ("features", ctypes.c_void_p)]
+                ("features", ctypes.c_void_p), ("wide", ctypes.c_void_p)]
 
 
 _lib = None
@@ -210,7 +210,8 @@ def _copy_out(ptr, n, dtype, device):
 
 TREE_FIELDS = (("level", torch.int32), ("min_index", torch.int32), ("parent", torch.int32),
                ("size", torch.int32), ("l2", torch.float32), ("a", torch.float32),
-               ("c", torch.float32), ("sx2", torch.float32), ("sv2", torch.float32))
+               ("c", torch.float32), ("sx2", torch.float32), ("sv2", torch.float32),
+               ("wide", torch.int32))
 
 
 def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_sub=10, f=0.7,

@@ -104,6 +104,71 @@ __global__ void k_p_fill(int64_t n, const float* __restrict__ x, const float* __
     deepest[i] = gid[r];
 }
 
+// Percolation of each 3D group: per axis the smallest and largest integer
+// displacement of its members from the reference member (the first packed
+// member, the smallest index), in the nearest periodic image exactly as for
+// the dispersions.  Stored offset by 2^62 so that unsigned atomics order
+// them; lanes of one group (members are packed per group) combine first.
+constexpr unsigned long long SPAN_OFF = 1ull << 62;
+
+__global__ void k_p_span_init(int32_t G, unsigned long long* __restrict__ span) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < 6 * (int64_t)G) span[i] = (i % 6) < 3 ? ~0ull : 0ull;
+}
+
+__global__ void k_p_span(int64_t n, const int32_t* __restrict__ flag,
+                         const int32_t* __restrict__ rex, const int32_t* __restrict__ rstart,
+                         const int32_t* __restrict__ keep, const int32_t* __restrict__ gid,
+                         const int32_t* __restrict__ goff, Members A, int64_t LQ,
+                         unsigned long long* __restrict__ span) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool ok = p < n;
+    const int32_t r = ok ? rex[p] + flag[p] - 1 : 0;
+    ok = ok && keep[r];
+    const int32_t g = ok ? gid[r] : -1;
+    unsigned long long d[3] = {SPAN_OFF, SPAN_OFF, SPAN_OFF};
+    if (ok) {
+        const int64_t ref = goff[r], pos = ref + (p - rstart[r]);
+        const float* ax3[3] = {A.x, A.y, A.z};
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            int64_t q = quant_pos(ax3[ax][pos]) - quant_pos(ax3[ax][ref]);
+            if (2 * q > LQ) q -= LQ;
+            else if (2 * q <= -LQ) q += LQ;
+            d[ax] = (unsigned long long)(q + (int64_t)SPAN_OFF);
+        }
+    }
+    uint64_t todo = __ballot(ok);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t lg = __shfl(g, leader, 64);
+        const bool mine = ok && g == lg;
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            const unsigned long long mn = wave_min_u64(mine ? d[ax] : ~0ull);
+            const unsigned long long mx = ~wave_min_u64(mine ? ~d[ax] : ~0ull);
+            if ((int)(threadIdx.x & 63) == leader) {
+                atomicMin(span + 6 * (int64_t)lg + ax, mn);
+                atomicMax(span + 6 * (int64_t)lg + 3 + ax, mx);
+            }
+        }
+        todo &= ~__ballot(mine);
+    }
+}
+
+// a group percolates when on some axis 2 * (max - min) >= L_Q
+__global__ void k_p_wide(int32_t G, const unsigned long long* __restrict__ span, int64_t LQ,
+                         int32_t* __restrict__ wide0) {
+    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    int32_t w = 0;
+    for (int ax = 0; ax < 3; ax++) {
+        const unsigned long long mn = span[6 * (int64_t)g + ax], mx = span[6 * (int64_t)g + 3 + ax];
+        if (2 * (int64_t)(mx - mn) >= LQ) w = 1;
+    }
+    wide0[g] = w;
+}
+
 // level-0 records; small groups into the bucket lists, large ones listed
 __global__ void k_p_class(int32_t nruns, const int32_t* __restrict__ rstart,
                           const int32_t* __restrict__ keep, const int32_t* __restrict__ gid,
@@ -163,6 +228,18 @@ __global__ void k_o_nodes(int32_t m, const int32_t* __restrict__ order,
     t.c[r] = nr.c[s];
     t.sx2[r] = nr.sx2[s];
     t.sv2[r] = nr.sv2[s];
+}
+
+// a node carries the percolation flag of its 3D group (level-0 ancestor,
+// whose record slot is the group id)
+__global__ void k_o_wide(int32_t m, const int32_t* __restrict__ order,
+                         const int32_t* __restrict__ tparent, const int32_t* __restrict__ wide0,
+                         int32_t* __restrict__ out) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    int32_t a = r;
+    while (tparent[a] >= 0) a = tparent[a];
+    out[r] = wide0[order[a]];
 }
 
 __global__ void k_o_feat(int32_t m, const int32_t* __restrict__ order,
@@ -228,6 +305,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     add(4 * (size_t)cap);                                      // canon
     const int64_t bstride = n / (min_group > 1 ? min_group : 1) + 2;   // groups per bucket, at most
     add(sizeof(SmallItem) * 4 * (size_t)bstride);              // level-0 buckets
+    add(8 * 6 * (size_t)bstride); add(4 * (size_t)bstride);    // group extents, percolation
     add(sizeof(ChildOut) * (size_t)(n / (SMALL_MAX + 1) + 2));
     add(sort_temp_bytes(cap > n ? cap : n)); add(scan_temp_bytes(n)); add(256);
     const bool want_feat = pp.want_feat != 0;
@@ -271,6 +349,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     int32_t* order = take<int32_t>(ar, cap);
     int32_t* canon = take<int32_t>(ar, cap);
     SmallItem* buckets = take<SmallItem>(ar, 4 * bstride);
+    unsigned long long* gspan = take<unsigned long long>(ar, 6 * bstride);
+    int32_t* wide0 = take<int32_t>(ar, bstride);
     ChildOut* large0 = take<ChildOut>(ar, n / (SMALL_MAX + 1) + 2);
     size_t stb = sort_temp_bytes(cap > n ? cap : n);
     void* stemp = arena_take(ar, stb);
@@ -318,6 +398,14 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
                                                               nr, buckets, bstride, ctr + 8,
                                                               large0, ctr + 12);
     RS_HIP(hipGetLastError());
+    // percolation flags of the groups; only the output reads them, so the
+    // batched form runs them on the side stream of the level-0 subtrees
+    auto span_pass = [&](hipStream_t s) {
+        if (G <= 0) return;
+        k_p_span_init<<<grid_for(6 * (int64_t)G, BT, 1ll << 31), BT, 0, s>>>(G, gspan);
+        k_p_span<<<gb, BT, 0, s>>>(n, flag, rex, rstart, keep, gid, goff, A, pp.LQ, gspan);
+        k_p_wide<<<grid_for(G, BT, 1ll << 31), BT, 0, s>>>(G, gspan, pp.LQ, wide0);
+    };
     RS_TRY(fill_i32(nr.count, G, 1, st));
     RS_HIP(hipMemcpyAsync(hc, ctr, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
@@ -384,6 +472,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         RS_HIP(hipStreamSynchronize(st));
         std::sort(hs.begin(), hs.end(),
                   [](const SmallItem& a, const SmallItem& b) { return a.slot < b.slot; });
+        span_pass(st);
+        RS_HIP(hipGetLastError());
         SmallItem* one = buckets;   // reuse: the host copy is complete
         size_t si = 0, li = 0;
         while (si < hs.size() || li < large.size()) {
@@ -420,7 +510,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         lw.side_pending = false;
         RS_HIP(hipEventRecord(ready, st));
         RS_HIP(hipStreamWaitEvent(s2, ready, 0));
-        int rc = RS_OK;
+        span_pass(s2);
+        int rc = hipGetLastError() == hipSuccess ? RS_OK : RS_EDEVICE;
         for (int b = 3; b >= 0 && rc == RS_OK; b--)
             rc = run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, s2,
                                   "phase_small_level0");
@@ -474,7 +565,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     }
     size_t nodes_bytes = arena_round(4 * (size_t)(m > 0 ? m : 1));
     size_t feat_bytes = want_feat ? arena_round(4 * (size_t)(m > 0 ? m : 1) * RS_NFEAT) : 0;
-    size_t total = 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)) + feat_bytes;
+    size_t total = 10 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)) + feat_bytes;
     rs_tree* t = (rs_tree*)calloc(1, sizeof(rs_tree));
     if (!t) return RS_ENOMEM;
     char* blk = nullptr;
@@ -500,9 +591,10 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     t->c = (float*)(blk + 6 * nodes_bytes);
     t->sx2 = (float*)(blk + 7 * nodes_bytes);
     t->sv2 = (float*)(blk + 8 * nodes_bytes);
-    t->deepest = (int32_t*)(blk + 9 * nodes_bytes);
+    t->wide = (int32_t*)(blk + 9 * nodes_bytes);
+    t->deepest = (int32_t*)(blk + 10 * nodes_bytes);
     t->features = want_feat
-        ? (float*)(blk + 9 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)))
+        ? (float*)(blk + 10 * nodes_bytes + arena_round(4 * (size_t)(n > 0 ? n : 1)))
         : nullptr;
     t->n_accepted = n_acc;
     t->n_fallback = n_fb;
@@ -510,7 +602,10 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     if (want_feat && m > 0)
         k_o_feat<<<grid_for((int64_t)m * RS_NFEAT, BT, 1ll << 31), BT, 0, st>>>(m, order, nr.feat,
                                                                              t->features);
-    if (m > 0) k_o_nodes<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, canon, nr, *t);
+    if (m > 0) {
+        k_o_nodes<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, canon, nr, *t);
+        k_o_wide<<<grid_for(m, BT, 1ll << 31), BT, 0, st>>>(m, order, t->parent, wide0, t->wide);
+    }
     if (n > 0) k_o_deep<<<gb, BT, 0, st>>>(n, deepest, canon, t->deepest);
     if (hipGetLastError() != hipSuccess) rc = RS_EDEVICE;
     int32_t last_level = -1;

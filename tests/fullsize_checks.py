@@ -16,7 +16,7 @@ import numpy as np
 
 import oracle
 
-FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2")
+FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide")
 WORKERS = 16
 
 
@@ -85,7 +85,7 @@ def check_subtree(R, cfg, g, root_of, canon_root):
     if sub.size != ref["level"].size:
         return [f"group {g}: {sub.size} nodes, oracle {ref['level'].size}"]
     bad = []
-    for k in ("level", "size", "l2", "a", "c", "sx2", "sv2"):
+    for k in ("level", "size", "l2", "a", "c", "sx2", "sv2", "wide"):
         if not np.array_equal(T[k][sub], ref[k]):
             bad.append(f"group {g}: field {k}")
     if not np.array_equal(T["min_index"][sub], mem[ref["min_index"]]):

@@ -14,7 +14,7 @@ import paper_2412_18629_amd as rs
 from paper_2412_18629_amd import learn, synth
 
 pytestmark = pytest.mark.gpu
-FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "deepest")
+FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide", "deepest")
 
 
 def _workload(n, seed, device="cuda"):

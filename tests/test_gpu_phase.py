@@ -15,7 +15,7 @@ from paper_2412_18629_amd import synth
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
-FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2")
+FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide")
 
 
 def _dev(arrs):
@@ -186,3 +186,27 @@ def test_tree_overflow_rebuild_equals(monkeypatch):
     got = rs.rs_phase_fof_batch(*arrs, cfg.box, lab)
     monkeypatch.delenv("RS_DEBUG_TREE_ENTRIES")
     _fields_equal(ref, got)
+
+
+def test_percolation_flags_match_oracle():
+    # chains of known extent (half the box and more set the flag, shorter
+    # ones and one across the periodic face do not) beside compact clumps
+    rng = np.random.default_rng(11)
+    L = 10.0
+    parts = []
+    for x0, y0, steps in ((1.0, 1.0, 40), (1.0, 3.0, 39), (8.0, 5.0, 32), (8.0, 7.0, 48)):
+        xs = np.mod(x0 + 0.125 * np.arange(steps + 1), L)
+        pos = np.stack([xs, np.full_like(xs, y0), np.full_like(xs, 4.0)], 1)
+        vel = np.zeros((steps + 1, 3))
+        vel[(steps + 1) // 2:, 0] = 3000.0
+        parts.append((pos, vel))
+    for c in range(6):
+        ctr = np.array([1.0 + 1.5 * c, 9.0, 8.0])
+        parts.append((ctr + rng.normal(0, 0.05, (300, 3)), rng.normal(0, 50.0, (300, 3))))
+    pos = np.mod(np.concatenate([p for p, _ in parts]), L).astype(F32)
+    vel = np.concatenate([v for _, v in parts]).astype(F32)
+    arrs = [pos[:, 0], pos[:, 1], pos[:, 2], vel[:, 0], vel[:, 1], vel[:, 2]]
+    lab = oracle.fof3d(*arrs[:3], L, 0.2)
+    got, ref = run_both(arrs, L, lab)
+    assert ref["wide"].sum() > 0 and (ref["wide"] == 0).sum() > 0
+    compare(got, ref)

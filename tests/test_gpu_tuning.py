@@ -11,7 +11,7 @@ import paper_2412_18629_amd as rs
 from paper_2412_18629_amd import autotune, learn, synth
 
 pytestmark = pytest.mark.gpu
-FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "deepest")
+FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide", "deepest")
 
 
 @pytest.fixture(scope="module")

@@ -258,3 +258,41 @@ def test_translation_invariance_on_dyadic_grid():
     for k in ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2"):
         assert np.array_equal(res[k], res_m[k]), k
     assert np.array_equal(res["deepest"], res_m["deepest"])
+
+
+def _chain(x0, steps, L):
+    """Particles 0.125 apart along x from x0 (wrapped into [0, L)) at fixed
+    y, z, in index order along the chain; the second half moves at 3000 km/s,
+    the first is at rest, so every pair within a half ties at the linking
+    length and the 6D pass splits the group into its two halves."""
+    xs = np.mod(x0 + 0.125 * np.arange(steps + 1), L)
+    pos = np.stack([xs, np.full_like(xs, 2.0), np.full_like(xs, 3.0)], 1).astype(F32)
+    vel = np.zeros((steps + 1, 3))
+    vel[(steps + 1) // 2:, 0] = 3000.0
+    return pos, vel.astype(F32)
+
+
+@pytest.mark.parametrize("x0,steps,expect", [(1.0, 40, 1), (1.0, 39, 0), (8.0, 32, 0),
+                                             (8.0, 48, 1)])
+def test_percolation_flag_chain_extent(x0, steps, expect):
+    # a chain of extent 0.125 * steps in a box of side 10: 5.0 (half the box)
+    # sets the flag, 4.875 does not; a chain across the periodic face is
+    # measured in the nearest image (4.0 clear, 6.0 set); every node of the
+    # group's hierarchy carries the group's flag
+    L = 10.0
+    pos, vel = _chain(x0, steps, L)
+    lab = oracle.fof3d(*pos.T, L, 0.2)
+    assert np.all(lab == lab[0])
+    res = oracle.phase_fof(*pos.T, *vel.T, L, lab)
+    assert res["level"].max() >= 1
+    assert res["wide"][0] == expect
+    assert np.all(res["wide"] == expect)
+
+
+def test_percolation_flag_clear_for_compact_groups():
+    # the 32^3 workload's haloes are far smaller than half its box
+    cfg = synth.CONFIGS["c32"]
+    x, y, z, vx, vy, vz = _np(synth.generate(cfg, 0))
+    lab = oracle.fof3d(x, y, z, cfg.box, cfg.link_len)
+    res = oracle.phase_fof(x, y, z, vx, vy, vz, cfg.box, lab)
+    assert res["level"].size > 0 and not res["wide"].any()
