@@ -21,6 +21,7 @@
 //   5. labels: flatten, smallest original index per root, scatter to the
 //              caller's label array.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -497,9 +498,14 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     }
     RS_HIP(hipGetLastError());
 
+    int64_t qcap = std::min<int64_t>(cap_heavy, INT32_MAX);
+    // test hook: a smaller queue sends the pairs beyond it down the inline path
+    if (const char* e = getenv("RS_DEBUG_HEAVY_QUEUE")) {
+        const int64_t v = atoll(e);
+        if (v >= 0 && v < qcap) qcap = v;
+    }
     LinkArgs A{oct_start, oct_bits, cell_oct, cell_key, row_start, n_cell, kout, sx, sy, sz,
-               g.autolink ? poct : parent, n_oct, g, heavy, n_heavy,
-               (int32_t)std::min<int64_t>(cap_heavy, INT32_MAX)};
+               g.autolink ? poct : parent, n_oct, g, heavy, n_heavy, (int32_t)qcap};
     prof_begin("fof3d_link", st);
     if (g.autolink) {
         RS_TRY(fill_i32(n_heavy, 0, 1, st));

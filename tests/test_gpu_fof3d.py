@@ -62,6 +62,22 @@ def test_small_box_few_cells():
         _check(pos, L, ll)
 
 
+@pytest.mark.parametrize("queue", ["0", "8"])
+def test_heavy_pair_queue_overflow(monkeypatch, queue):
+    # dense clumps give octant pairs of more than 1024 member pairs; with the
+    # deferred-pair queue shrunk to nothing or to a few entries, the pairs
+    # beyond it are tested inline by their octant's thread instead
+    rng = np.random.default_rng(13)
+    L = 8.0
+    centres = rng.random((12, 3)) * L
+    pos = centres[rng.integers(0, 12, 60000)] + rng.normal(0, 0.06, (60000, 3))
+    pos = np.mod(pos, L).astype(F32)
+    pos[pos >= L] = 0
+    monkeypatch.setenv("RS_DEBUG_HEAVY_QUEUE", queue)
+    _check(pos, L, 0.2)
+    monkeypatch.delenv("RS_DEBUG_HEAVY_QUEUE")
+
+
 def test_sparse_grid_rows_by_search():
     # ~2000^2 cell rows for 20k particles: no dense row table, each row's
     # cells are found by binary search over all cell keys; clumps straddle
