@@ -486,10 +486,10 @@ typedef struct {
 } node_t;
 
 /*
- * Percolation flag of a 3D group (SURVEY reading C13): on some axis the
- * members' integer displacements from the reference member, brought to the
- * nearest periodic image exactly as for the dispersions, span at least half
- * the box (2 * (max - min) >= L_Q).  The nearest-image frame of such a group
+ * Percolation flag of a 3D group: on some axis the members' integer
+ * displacements from the reference member, brought to the nearest periodic
+ * image exactly as for the dispersions, span at least half the box
+ * (2 * (max - min) >= L_Q).  The nearest-image frame of such a group
  * is not unique, so its dispersions, and through them every node of its
  * hierarchy, are not invariant under translation; the children inherit it.
  */
