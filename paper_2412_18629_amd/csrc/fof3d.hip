@@ -14,12 +14,16 @@
 //              are a sorted run; a dense row table gives each row's run
 //              (when the grid has few rows for the particle count, else the
 //              run is found by binary search over all cell keys).
-//   4. link:   union-find over sorted slots.  An octant is one element
-//              (its first slot); octant pairs in the 27-cell neighbourhood
-//              are tested with early exit on the first linked pair, and
-//              skipped when already in one component.
-//   5. labels: flatten, smallest original index per root, scatter to the
-//              caller's label array.
+//   4. link:   union-find over octants (one element each, its members
+//              being linked already); octant pairs in the 27-cell
+//              neighbourhood are tested with early exit on the first linked
+//              pair and skipped when already in one component.  Pairs of
+//              more than HEAVY_PAIRS member pairs are queued and tested
+//              afterwards, one wavefront per pair.  Without auto-link (grids
+//              of under three cells per axis, or octants too wide) the
+//              union-find runs over slots and every member pair is tested.
+//   5. labels: flatten, slot parents from the octant roots, smallest
+//              original index per root, scatter to the caller's labels.
 #include <algorithm>
 #include <cstdlib>
 

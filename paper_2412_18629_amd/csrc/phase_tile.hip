@@ -6,7 +6,9 @@
 // is then loaded once (one member per lane) and only the queries whose own
 // exact bound admits the leaf are replayed against it: each such query is
 // broadcast to the lanes, every lane evaluates the pair with its member.
-// Candidate data is read once per tile instead of once per query.
+// Candidate data is read once per tile instead of once per query.  The walk
+// scans up to four stack entries per pass (cells average about ten
+// children), and linked pairs are united in batches of 64.
 #include <type_traits>
 
 #include "phase_common.h"

@@ -11,13 +11,12 @@
 // velocities), so boxes are tight at every level.
 //
 // Traversal: one wavefront handles one query at a time.  The 64 lanes bound
-// 64 child boxes in parallel; surviving leaves are scanned one candidate per
-// lane, surviving internal children go onto a per-wavefront LDS stack.
+// 64 child boxes in parallel (two cells of at most 32 children share a
+// pass); surviving leaves are scanned one candidate per lane, surviving
+// internal children go onto a per-wavefront LDS stack, the nearest on top.
 #include "phase_common.h"
 
 namespace rs {
-
-
 
 constexpr uint64_t MORTON_MASK = (1ull << 42) - 1ull;
 constexpr int TREE_LEVELS = 7;       // 42 Morton bits, 6 per level
