@@ -64,8 +64,8 @@ enum {
 #define RS_MLP_NPARAM 5825
 
 /*
- * rs_fof3d -- 3D friends-of-friends over one periodic box (paper,
- * Parallelization section: "each process performs 3D FoF").
+ * rs_fof3d -- 3D friends-of-friends over one periodic box (the per-process
+ * FoF pass of the paper's Parallelization section).
  *
  * Groups are the connected components of the pair relation D(i,j) <= ll^2
  * with ll = link_len (an absolute length; a caller following the paper's
