@@ -237,12 +237,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
 // earlier octants, whose pairs with this one are taken from their side.
 template <bool AUTOLINK>
 __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
-    // two threads per octant: part 0 takes the neighbour cells of the rows
-    // at dz = -1 and 0, part 1 those at dz = +1, which halves the serial
-    // chain of dependent loads each thread walks
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int32_t a = (int32_t)(tid >> 1);
-    const int part = (int)(tid & 1);
+    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= A.n_oct) return;
     const Grid3& g = A.g;
     const int32_t s0 = A.oct_start[a], s1 = A.oct_start[a + 1];
@@ -254,7 +249,7 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
     const int64_t cy = (int64_t)(row % (uint64_t)nc);
     const int64_t cz = (int64_t)(row / (uint64_t)nc);
 
-    if (!AUTOLINK && part == 0) {
+    if (!AUTOLINK) {
         for (int32_t i = s0; i < s1; i++) {
             const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
             for (int32_t j = i + 1; j < s1; j++)
@@ -265,7 +260,7 @@ __global__ void __launch_bounds__(256) k_link(LinkArgs A) {
     int32_t ra = AUTOLINK ? a : s0;
     // x - 1 .. x + 1 are one contiguous key range unless x wraps
     const bool inner = nc >= 3 && cx >= 1 && cx <= nc - 2;
-    for (int dz = part ? 1 : -1; dz <= (part ? 1 : 0); dz++) {
+    for (int dz = -1; dz <= 1; dz++) {
         int64_t nz = cz + dz;
         nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
         for (int dy = -1; dy <= 1; dy++) {
@@ -500,7 +495,6 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
         k_row_start<<<grid_for((int64_t)rows + 1, BT, 1ll << 31), BT, 0, st>>>(
             cell_key, n_cell, g.nc, (int64_t)rows, row_start);
     unsigned go = grid_for(n_oct, 256, 1ll << 31);
-    unsigned go2 = grid_for(2 * (int64_t)n_oct, 256, 1ll << 31);
     if (g.autolink) {
         k_iota<<<go, 256, 0, st>>>(n_oct, poct);
     } else {
@@ -519,10 +513,10 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     prof_begin("fof3d_link", st);
     if (g.autolink) {
         RS_TRY(fill_i32(n_heavy, 0, 1, st));
-        k_link<true><<<go2, 256, 0, st>>>(A);
+        k_link<true><<<go, 256, 0, st>>>(A);
         k_link_heavy<<<HEAVY_BLOCKS, 64, 0, st>>>(A);
     } else {
-        k_link<false><<<go2, 256, 0, st>>>(A);
+        k_link<false><<<go, 256, 0, st>>>(A);
     }
     RS_HIP(hipGetLastError());
     prof_end("fof3d_link", st, (double)n);
