@@ -1,0 +1,77 @@
+"""Host-side logic of bench.py (CPU only): several GPUs are refused, the PMC
+summary calibrates the byte counters against the plain copy kernel and
+computes the vector-ALU occupancy, and a traffic figure is used only while
+its kernel's sources are unchanged."""
+import csv
+import json
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _write(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+    return str(path)
+
+
+def _row(d, name, counter, value):
+    return {"Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
+            "Counter_Value": value}
+
+
+def test_several_gpus_refused():
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_pmc_summary_calibration_and_occupancy(tmp_path):
+    mib = 64
+    kib = mib * 1024.0
+    link = bench.KERNEL_SYMBOL["phase_large_link"][0] + "true>(rs::TArgs, int, int)"
+    # the copy kernel moves `mib` MiB: its FETCH_SIZE reads half of that
+    # (scale 2), its WRITE_SIZE all of it (scale 1); a counter is summed over
+    # the rows (instances) of one dispatch
+    fetch = [_row(d, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 4) for d in (1, 1, 2, 2, 3, 3)]
+    write = [_row(d, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib) for d in (1, 2, 3)]
+    fetch += [_row(10, link, "FETCH_SIZE", 600.0), _row(10, link, "FETCH_SIZE", 400.0),
+              _row(11, link, "FETCH_SIZE", 3000.0)]
+    write += [_row(10, link, "WRITE_SIZE", 10.0), _row(11, link, "WRITE_SIZE", 30.0)]
+    valu = [_row(10, link, "SQ_ACTIVE_INST_VALU", 5.0e6), _row(11, link, "SQ_ACTIVE_INST_VALU", 3.0e6),
+            _row(10, link, "GRBM_GUI_ACTIVE", 8.0e4), _row(11, link, "GRBM_GUI_ACTIVE", 8.0e4)]
+    out = tmp_path / "summary.json"
+    res = bench.pmc_summary(_write(tmp_path / "f.csv", fetch), _write(tmp_path / "w.csv", write),
+                            mib << 20, "cmd", str(out), _write(tmp_path / "v.csv", valu))
+    assert res["calibration"]["fetch_scale"] == 2.0
+    assert res["calibration"]["write_scale"] == 1.0
+    k = res["kernels"]["phase_large_link"]
+    assert k["launches"] == 2
+    # per launch (fetch x 2 + write x 1) KiB, averaged over the launches
+    assert k["hbm_bytes_per_launch"] == ((1000 * 2 + 10) + (3000 * 2 + 30)) / 2 * 1024.0
+    # 4 cycles per VALU instruction over 1024 SIMDs x kernel cycles (summed over 8 XCDs)
+    assert k["valu_busy"] == pytest.approx(8.0e6 * 4 / (1.6e5 / 8 * 1024))
+    assert json.loads(out.read_text())["kernels"]["phase_large_link"]["launches"] == 2
+
+
+def test_traffic_only_while_sources_unchanged(tmp_path, monkeypatch):
+    path = tmp_path / "summary.json"
+    entry = {"hbm_bytes_per_launch": 123.0,
+             "sources_sha256": bench.source_digest("phase_large_link")}
+    path.write_text(json.dumps({"workload": "c512", "kernels": {"phase_large_link": entry}}))
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(path))
+    assert bench.measured_pmc("phase_large_link", "c512", "hbm_bytes_per_launch") == 123.0
+    assert bench.measured_pmc("phase_large_link", "c256", "hbm_bytes_per_launch") is None
+    assert bench.measured_pmc("phase_large_nn", "c512", "hbm_bytes_per_launch") is None
+    entry["sources_sha256"] = "0" * 64
+    path.write_text(json.dumps({"workload": "c512", "kernels": {"phase_large_link": entry}}))
+    assert bench.measured_pmc("phase_large_link", "c512", "hbm_bytes_per_launch") is None
