@@ -236,7 +236,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
 // with a smaller key (among them every cell of an earlier row) hold only
 // earlier octants, whose pairs with this one are taken from their side.
 template <bool AUTOLINK>
-__global__ void __launch_bounds__(256) k_link(LinkArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_link(LinkArgs A) {
     const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= A.n_oct) return;
     const Grid3& g = A.g;
