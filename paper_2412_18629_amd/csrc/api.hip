@@ -38,7 +38,7 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float bo
         if (n_groups) *n_groups = 0;
         return RS_OK;
     }
-    RS_TRY(rs::arena_call_begin(1u << rs::AR_3D));
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
                          static_cast<hipStream_t>(stream));
 }
@@ -56,7 +56,7 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
     if ((flags & 0xffu) == RS_LEARNED && !model) return RS_EINVAL;
     if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !fof_labels)) return RS_EINVAL;
     RS_TRY(rs::device_ready());
-    RS_TRY(rs::arena_call_begin((1u << rs::AR_PHASE) | (1u << rs::AR_LARGE) |
+    RS_TRY(rs::arena_call_begin((1u << rs::AR_BASE) | (1u << rs::AR_LARGE) |
                                 (1u << rs::AR_TREE) | (1u << rs::AR_MLP)));
     return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,
                          model, out, static_cast<hipStream_t>(stream));

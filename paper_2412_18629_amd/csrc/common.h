@@ -176,16 +176,21 @@ inline int hip_status(hipError_t e) {
 
 // Grow-only per-device workspaces with a bump allocator.  A call reserves
 // the footprint of one phase once, then carves sub-buffers (256-byte
-// aligned).  Indices: AR_3D, AR_PHASE / AR_LARGE / AR_TREE (6D pass), AR_MLP
-// (proposer network), AR_SORT (standalone sort).
+// aligned).  AR_BASE holds either the 3D pass's work space or the 6D pass's
+// level-0 tables: both entry points synchronise their stream before they
+// return, so the two are never live together and share one allocation (at
+// 1024^3 each is about 100 GiB; two would not fit beside the large-node work
+// space, and re-allocating them on every call costs seconds).  AR_LARGE and
+// AR_TREE are the 6D pass's level pipeline, AR_MLP the proposer network,
+// AR_SORT the standalone sort.
 struct Arena {
     char* base = nullptr;
     size_t cap = 0;
     size_t off = 0;
 };
 
-constexpr int N_ARENAS = 6;
-constexpr int AR_3D = 0, AR_PHASE = 1, AR_LARGE = 2, AR_MLP = 3, AR_SORT = 4, AR_TREE = 5;
+constexpr int N_ARENAS = 5;
+constexpr int AR_BASE = 0, AR_LARGE = 1, AR_MLP = 2, AR_SORT = 3, AR_TREE = 4;
 // The arenas an API call uses; when a reservation cannot be met, the
 // device's other arenas (left by earlier calls of other phases) are
 // released and the allocation is tried again.

@@ -440,7 +440,7 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
     Arena* ar;
-    RS_TRY(arena_reserve(AR_3D, bytes, &ar));
+    RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
     uint64_t* kin = take<uint64_t>(ar, n);
     uint64_t* kout = take<uint64_t>(ar, n);
     int32_t* vin = take<int32_t>(ar, n);

@@ -313,7 +313,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     const size_t model_floats = 2 * RS_NFEAT + RS_MLP_NPARAM;
     add(4 * model_floats);
     Arena* ar;
-    RS_TRY(arena_reserve(AR_PHASE, bytes, &ar));
+    RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
     uint64_t* lkin = take<uint64_t>(ar, n);
     uint64_t* lkout = take<uint64_t>(ar, n);
     int32_t* lvin = take<int32_t>(ar, n);
