@@ -15,9 +15,13 @@
 
 namespace rs {
 
+// LDS per wavefront stays under 5 KB, so that eight wavefronts fit per SIMD:
+// the link is bound by the latency of its walks and replays, and more
+// resident wavefronts hide more of it than larger buffers save
 constexpr int TSTACK = 520;   // >= 64 internal children x 8 levels
-constexpr int TLIST = 256;    // candidate leaves buffered before processing
-constexpr int THITS = 256;    // linked pairs buffered before their unions
+constexpr int TLIST = 96;     // candidate leaves buffered before processing (>= 64)
+constexpr int THITS = 64;     // linked pairs buffered before their unions (>= 64)
+static_assert(TLIST >= 64 && THITS >= 64, "one pass adds up to 64 leaves or pairs");
 
 struct TileRec {
     float lo[6], hi[6];

@@ -75,3 +75,20 @@ def test_traffic_only_while_sources_unchanged(tmp_path, monkeypatch):
     entry["sources_sha256"] = "0" * 64
     path.write_text(json.dumps({"workload": "c512", "kernels": {"phase_large_link": entry}}))
     assert bench.measured_pmc("phase_large_link", "c512", "hbm_bytes_per_launch") is None
+
+
+def test_nn_refinement_dispatches_kept_apart(tmp_path):
+    # at each level the learned form runs the NN bracket pass, the acceptance
+    # of the brackets, then (when some were rejected) the refinement pass with
+    # the same kernel; only the bracket passes count as phase_large_nn
+    nn = bench.KERNEL_SYMBOL["phase_large_nn"][0] + "true>(rs::TArgs, int, int, float*)"
+    seq = [(1, "rs::k_lbracket(int, float const*, rs::LParam*)", 0.0), (2, nn, 900.0),
+           (3, "rs::k_lcount(...)", 0.0), (4, "rs::k_laccept(int, int const*, rs::LParam*, int*)", 0.0),
+           (5, "__amd_rocclr_copyBuffer", 0.0), (6, nn, 20.0),
+           (7, "rs::k_lhist(...)", 0.0), (8, "rs::k_lbracket(int, float const*, rs::LParam*)", 0.0),
+           (9, nn, 300.0), (10, "rs::k_laccept(int, int const*, rs::LParam*, int*)", 0.0)]
+    rows = {d: (n, v) for d, n, v in seq}
+    assert bench._kernel_values(rows, "phase_large_nn") == [900.0, 300.0]
+    # the batched form has no brackets: every NN dispatch is the exact pass
+    rows = {1: (nn, 5.0), 2: ("rs::k_lhist(...)", 0.0), 3: (nn, 7.0)}
+    assert bench._kernel_values(rows, "phase_large_nn") == [5.0, 7.0]
