@@ -353,6 +353,28 @@ struct StackEnt {
     float lb;
 };
 
+// A stack entry in LDS takes 8 bytes, so that eight wavefronts fit per SIMD
+// (the search is bound by the latency of its dependent loads).  The child
+// count (1..64) sits in the low six bits of the lower bound, whose value is
+// truncated there: truncating a non-negative float only lowers it, so the
+// stored bound still prunes nothing that the exact one would keep.  A finest
+// cell can have more than 64 children (leaves of members that share the full
+// Morton prefix); it is stored as the negated entry index of the cell, and
+// its child range is read back from the cell's record when it is popped.
+struct StackSlot {
+    int32_t cfirst;
+    uint32_t pk;
+};
+
+RS_DEV StackSlot stack_pack(int32_t entry, int32_t cfirst, int32_t ccount, float lb) {
+    const uint32_t b = __float_as_uint(lb) & ~63u;
+    return ccount <= 64 ? StackSlot{cfirst, b | (uint32_t)(ccount - 1)} : StackSlot{-1 - entry, b};
+}
+
+RS_DEV StackEnt stack_unpack(StackSlot s) {
+    return StackEnt{s.cfirst, (int32_t)(s.pk & 63u) + 1, __uint_as_float(s.pk & ~63u)};
+}
+
 // nearest-neighbour d^2 of every member (exact): own leaf first, then a
 // depth-first descent from the node's root.  One wavefront per tile of
 // queries, one query at a time; child records are bounded lane-parallel,
@@ -360,7 +382,7 @@ struct StackEnt {
 template <bool O32>
 __global__ void __launch_bounds__(64)
 k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
-    __shared__ StackEnt stk[STACK_PER_WAVE];
+    __shared__ StackSlot stk[STACK_PER_WAVE];
     const int lane = threadIdx.x;
     const int t = xcd_chunk_index(blockIdx.x, chunk);
     if (t >= ntiles) return;
@@ -399,20 +421,27 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
             if (m < r0[13] && m != qm) bl = fminf(bl, tq_d2<O32>(T, m, q, P, A.pp));
         }
         float best = wmin_nonneg(bl);
-        if (lane == 0) stk[0] = StackEnt{rf, rn, 0.0f};
+        // a node's root is never a finest cell: at most 64 children
+        if (lane == 0) stk[0] = stack_pack(0, rf, rn, 0.0f);
         int sp = best <= lo2 ? 0 : 1;
         __syncthreads();
         while (sp > 0) {
             sp--;
-            StackEnt se = stk[sp];
+            StackEnt se = stack_unpack(stk[sp]);
+            if (se.cfirst < 0) {
+                // finest cell with more than 64 leaves: its range from its record
+                const int2 cc = *reinterpret_cast<const int2*>(tb.erec + 16 * (int64_t)(-1 - se.cfirst) + 14);
+                se.cfirst = cc.x;
+                se.ccount = cc.y;
+            }
             // most cells have at most 32 children: the next entry, when it is
             // as small and still needed, is visited in the same pass on the
             // upper half of the lanes (the live entries of each depth still
             // come from one pass, at most 64, so the stack bound holds)
             StackEnt se2{0, 0, 0.0f};
             if (se.ccount <= 32 && sp > 0) {
-                const StackEnt t2 = stk[sp - 1];
-                if (t2.ccount <= 32 && (!cull || t2.lb < best)) {
+                const StackEnt t2 = stack_unpack(stk[sp - 1]);
+                if (t2.cfirst >= 0 && t2.ccount <= 32 && (!cull || t2.lb < best)) {
                     se2 = t2;
                     sp--;
                 }
@@ -443,7 +472,8 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                 const bool leaf = r.cfirst < 0;
                 const uint64_t imask = __ballot(need && !leaf);
                 if (need && !leaf)
-                    stk[sp + __popcll(imask & lanemask_lt())] = StackEnt{r.cfirst, r.ccount, lb};
+                    stk[sp + __popcll(imask & lanemask_lt())] =
+                        stack_pack(k, r.cfirst, r.ccount, lb);
                 if (cull && __popcll(imask) > 1) {
                     // the nearest internal child goes on top: visited first,
                     // it lowers `best` soonest and prunes its siblings
@@ -453,7 +483,7 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                         const int pos = sp + __popcll(imask & lanemask_lt());
                         const int top = sp + __popcll(imask) - 1;
                         if (pos != top) {
-                            const StackEnt e = stk[top];
+                            const StackSlot e = stk[top];
                             stk[top] = stk[pos];
                             stk[pos] = e;
                         }

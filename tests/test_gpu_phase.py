@@ -210,3 +210,23 @@ def test_percolation_flags_match_oracle():
     got, ref = run_both(arrs, L, lab)
     assert ref["wide"].sum() > 0 and (ref["wide"] == 0).sum() > 0
     compare(got, ref)
+
+
+@pytest.mark.parametrize("flags", [rs.RS_BATCHED, rs.RS_LEARNED])
+def test_large_node_with_coincident_core(flags):
+    # 4200 members at one point in phase space fill one finest cell of the
+    # search tree with 66 leaves (more than the 64 children other cells can
+    # have); the spread members around it reach that cell in their searches
+    from paper_2412_18629_amd import learn
+    rng = np.random.default_rng(12)
+    pos = np.concatenate([np.full((4200, 3), 5.0), 5.0 + rng.normal(0, 0.3, (1500, 3))])
+    vel = np.concatenate([np.full((4200, 3), 100.0), rng.normal(100.0, 200.0, (1500, 3))])
+    arrs = [np.ascontiguousarray(a, dtype=F32) for a in
+            (pos[:, 0], pos[:, 1], pos[:, 2], vel[:, 0], vel[:, 1], vel[:, 2])]
+    lab = np.zeros(pos.shape[0], np.int32)
+    model = learn.load_model() if flags == rs.RS_LEARNED else None
+    got = rs.rs_phase_fof_batch(*_dev(arrs), 20.0, torch.from_numpy(lab).cuda(), flags=flags,
+                                model=model)
+    ref = oracle.phase_fof(*arrs, 20.0, lab)
+    assert (ref["size"] > 2048).any()
+    compare(got, ref)
