@@ -22,9 +22,13 @@ namespace rs {
 enum { SH_SP, SH_S0, SH_SZ, SH_SLOT, SH_LEVEL, SH_REF, SH_NC, SH_NCH, SH_BASE, SH_OK, SH_TOT,
        SH_BUCKET, SH_KK, SH_NOWRAP, SH_N };
 
+// Per member 48 bytes: position and index, velocity and nearest-neighbour
+// d^2 (whose slot holds the component counts in step 5), parent, packed
+// component minimum, two 16-bit member lists.  At the default min_sub this
+// keeps three 1024-member workgroups per CU.
 size_t small_lds_bytes(int maxn, int min_sub) {
     int capn = maxn / min_sub + 1;
-    return (size_t)maxn * 52 + (size_t)capn * 5 * 4 + (size_t)capn * 6 * 4 + 64;
+    return (size_t)maxn * 48 + (size_t)capn * 5 * 4 + (size_t)capn * 6 * 4 + 64;
 }
 
 template <int MAXN, int NT, bool FEAT>
@@ -36,8 +40,7 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
     float4* P = reinterpret_cast<float4*>(smem);                  // x y z idx
     float4* V = P + MAXN;                                         // vx vy vz d2
     int32_t* par = reinterpret_cast<int32_t*>(V + MAXN);
-    int32_t* cnt = par + MAXN;
-    unsigned long long* mpk = reinterpret_cast<unsigned long long*>(cnt + MAXN);
+    unsigned long long* mpk = reinterpret_cast<unsigned long long*>(par + MAXN);
     uint16_t* perm = reinterpret_cast<uint16_t*>(mpk + MAXN);
     uint16_t* tmp = perm + MAXN;
     const int capn = MAXN / pp.min_sub + 1;
@@ -45,7 +48,12 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
     int32_t* ch = stk + 5 * capn;                                 // [capn][6]
     __shared__ unsigned long long acc[18];
     __shared__ uint32_t ext[6];
-    __shared__ int32_t hist[256];
+    // the 256-bin histogram of the select (and the feature bins) lives in the
+    // member list `tmp` where that is large enough: the two are never live
+    // together (steps 1-3 against steps 4-5, separated by barriers)
+    constexpr bool HIST_IN_TMP = MAXN >= 512;
+    __shared__ int32_t hist_own[HIST_IN_TMP ? 1 : 256];
+    int32_t* hist = HIST_IN_TMP ? reinterpret_cast<int32_t*>(tmp) : hist_own;
     __shared__ int32_t sh[SH_N];
     __shared__ float shf[4];
 
@@ -313,7 +321,7 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             for (int m = tid; m < sz; m += NT) {
                 int s = perm[s0 + m];
                 par[s] = lds_root(par, s);
-                cnt[s] = 0;
+                V[s].w = 0.0f;           // component count (exact small integers)
                 mpk[s] = ~0ull;
             }
             if (tid == 0) sh[SH_NCH] = 0;
@@ -321,7 +329,7 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             for (int m = tid; m < sz; m += NT) {
                 int s = perm[s0 + m];
                 int r = par[s];
-                atomicAdd(cnt + r, 1);
+                atomicAdd(&V[r].w, 1.0f);
                 unsigned long long key =
                     ((unsigned long long)(uint32_t)__float_as_int(P[s].w) << 16) | (unsigned)s;
                 atomicMin(mpk + r, key);
@@ -329,10 +337,11 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             __syncthreads();
             for (int m = tid; m < sz; m += NT) {
                 int s = perm[s0 + m];
-                if (par[s] == s && cnt[s] >= pp.min_sub && cnt[s] < sz) {
+                const int cs = (int)V[s].w;
+                if (par[s] == s && cs >= pp.min_sub && cs < sz) {
                     int c = atomicAdd(sh + SH_NCH, 1);
                     ch[6 * c + 0] = s;
-                    ch[6 * c + 1] = cnt[s];
+                    ch[6 * c + 1] = cs;
                     ch[6 * c + 2] = (int)(mpk[s] >> 16);
                     ch[6 * c + 3] = (int)(mpk[s] & 0xffffull);
                 }
@@ -363,12 +372,12 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
                         nr.minidx[cs] = ch[6 * c + 2];
                         nr.parent[cs] = slot;
                         nr.size[cs] = ch[6 * c + 1];
-                        cnt[ch[6 * c + 0]] = -(c + 1);
+                        V[ch[6 * c + 0]].w = (float)-(c + 1);
                     }
                     __syncthreads();
                     for (int m = tid; m < sz; m += NT) {
                         int s = perm[s0 + m];
-                        int cv = cnt[par[s]];
+                        int cv = (int)V[par[s]].w;
                         if (cv < 0) {
                             int c = -cv - 1;
                             int pos = ch[6 * c + 4] + atomicAdd(ch + 6 * c + 5, 1);
