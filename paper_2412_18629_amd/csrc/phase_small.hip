@@ -14,6 +14,8 @@
 //      range, children are pushed
 // The node's smallest-index member is the moment reference; children carry
 // theirs from the packed (index, slot) minimum of their component.
+#include <type_traits>
+
 #include "phase_common.h"
 
 namespace rs {
@@ -29,6 +31,20 @@ enum { SH_SP, SH_S0, SH_SZ, SH_SLOT, SH_LEVEL, SH_REF, SH_NC, SH_NCH, SH_BASE, S
 size_t small_lds_bytes(int maxn, int min_sub) {
     int capn = maxn / min_sub + 1;
     return (size_t)maxn * 48 + (size_t)capn * 5 * 4 + (size_t)capn * 6 * 4 + 64;
+}
+
+// minimum over the 64 lanes of a non-negative float (or +inf), uniform:
+// row steps by DPP, then two row broadcasts carry it to lane 63.  All 64
+// lanes must be active.
+RS_DEV float small_wmin_nonneg(float x) {
+    uint32_t v = __float_as_uint(x);
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xf, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xa, 0xf, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xc, 0xf, false));
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
 }
 
 template <int MAXN, int NT, bool FEAT>
@@ -184,6 +200,13 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
             }
 
             // ---- 2. nearest-neighbour distances ----
+            // Each pair is evaluated once, by the thread holding its earlier
+            // member (d^2 is symmetric bit for bit: the differences only
+            // change sign).  The later member's minimum is gathered over the
+            // wavefront and merged with an LDS atomic minimum on the d^2 bits
+            // (non-negative floats order like their bit patterns); a
+            // wavefront skips a candidate no member of its row precedes.
+            for (int m = tid; m < sz; m += NT) V[perm[s0 + m]].w = __builtin_huge_valf();
             {
                 float xi[R], yi[R], zi[R], ui[R], vi[R], wi[R], best[R];
                 int si[R];
@@ -197,35 +220,36 @@ k_small_subtree(const SmallItem* __restrict__ items, int n_items, Members mb, No
                     ui[r] = v.x; vi[r] = v.y; wi[r] = v.z;
                     best[r] = __builtin_huge_valf();
                 }
-                if (nowrap) {
-                    for (int jj = 0; jj < sz; jj++) {
-                        int j = perm[s0 + jj];
-                        float4 p = P[j], v = V[j];
-#pragma unroll
-                        for (int r = 0; r < R; r++) {
-                            float d = phase_d2<false>(xi[r], yi[r], zi[r], ui[r], vi[r], wi[r],
-                                                      p.x, p.y, p.z, v.x, v.y, v.z, fa, fc,
-                                                      pp.L, pp.h);
-                            best[r] = (j != si[r] && d < best[r]) ? d : best[r];
-                        }
-                    }
-                } else {
-                    for (int jj = 0; jj < sz; jj++) {
-                        int j = perm[s0 + jj];
-                        float4 p = P[j], v = V[j];
-#pragma unroll
-                        for (int r = 0; r < R; r++) {
-                            float d = phase_d2<true>(xi[r], yi[r], zi[r], ui[r], vi[r], wi[r],
-                                                     p.x, p.y, p.z, v.x, v.y, v.z, fa, fc, pp.L,
-                                                     pp.h);
-                            best[r] = (j != si[r] && d < best[r]) ? d : best[r];
-                        }
-                    }
-                }
                 __syncthreads();
+                auto scan = [&](auto wrap) {
+                    constexpr bool WRAP = decltype(wrap)::value;
+                    for (int jj = wave * 64 + 1; jj < sz; jj++) {
+                        const int j = perm[s0 + jj];
+                        const float4 p = P[j], v = V[j];
+                        float rev = __builtin_huge_valf();
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            if (jj > r * NT + wave * 64) {   // uniform over the wavefront
+                                const float d = phase_d2<WRAP>(xi[r], yi[r], zi[r], ui[r], vi[r],
+                                                               wi[r], p.x, p.y, p.z, v.x, v.y,
+                                                               v.z, fa, fc, pp.L, pp.h);
+                                const bool ok = tid + r * NT < jj;
+                                best[r] = ok && d < best[r] ? d : best[r];
+                                rev = ok ? fminf(rev, d) : rev;
+                            }
+                        }
+                        const float mn = small_wmin_nonneg(rev);
+                        if (lane == 0 && mn < __builtin_huge_valf())
+                            atomicMin(reinterpret_cast<uint32_t*>(&V[j].w), __float_as_uint(mn));
+                    }
+                };
+                if (nowrap) scan(std::false_type{});
+                else scan(std::true_type{});
 #pragma unroll
                 for (int r = 0; r < R; r++)
-                    if (si[r] >= 0) V[si[r]].w = best[r];
+                    if (si[r] >= 0)
+                        atomicMin(reinterpret_cast<uint32_t*>(&V[si[r]].w),
+                                  __float_as_uint(best[r]));
             }
             __syncthreads();
 
