@@ -4,8 +4,9 @@
 // splits it and every descendant without leaving LDS, using an explicit
 // stack.  Per node:
 //   1. exact integer moments (wave shuffles + LDS atomics) -> a, c
-//   2. nearest-neighbour d^2 of every member: all pairs, LDS broadcast reads,
-//      R members per thread held in registers
+//   2. nearest-neighbour d^2 of every member: every pair once, LDS broadcast
+//      reads, R members per thread held in registers, the later member's
+//      minimum by a wavefront reduction and an LDS atomic minimum
 //   3. l^2 = k-th smallest d^2 by a 4-pass 8-bit radix select in LDS
 //   4. links d^2 <= l^2 among members with d^2_i <= l^2 (others cannot link),
 //      lock-free union-find in LDS
