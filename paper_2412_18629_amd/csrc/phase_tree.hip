@@ -307,9 +307,10 @@ RS_DEV float tq_d2(const Members& T, int64_t m, const TQuery& q, const LParam& P
                    const PhaseParams& pp) {
     const float xj = mload<O32>(T.x, m), yj = mload<O32>(T.y, m), zj = mload<O32>(T.z, m);
     const float uj = mload<O32>(T.vx, m), vj = mload<O32>(T.vy, m), wj = mload<O32>(T.vz, m);
-    return P.nowrap
-        ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h)
-        : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a, P.c, pp.L, pp.h);
+    return P.nowrap ? phase_d2<false>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a,
+                                      P.c, pp.L, pp.h)
+                    : phase_d2<true>(q.x, q.y, q.z, q.u, q.v, q.w, xj, yj, zj, uj, vj, wj, P.a,
+                                     P.c, pp.L, pp.h);
 }
 
 // one child-entry record, read with four 16-byte loads
@@ -368,7 +369,8 @@ struct StackSlot {
 
 RS_DEV StackSlot stack_pack(int32_t entry, int32_t cfirst, int32_t ccount, float lb) {
     const uint32_t b = __float_as_uint(lb) & ~63u;
-    return ccount <= 64 ? StackSlot{cfirst, b | (uint32_t)(ccount - 1)} : StackSlot{-1 - entry, b};
+    if (ccount <= 64) return StackSlot{cfirst, b | (uint32_t)(ccount - 1)};
+    return StackSlot{-1 - entry, b};
 }
 
 RS_DEV StackEnt stack_unpack(StackSlot s) {
@@ -430,7 +432,8 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
             StackEnt se = stack_unpack(stk[sp]);
             if (se.cfirst < 0) {
                 // finest cell with more than 64 leaves: its range from its record
-                const int2 cc = *reinterpret_cast<const int2*>(tb.erec + 16 * (int64_t)(-1 - se.cfirst) + 14);
+                const float* rec = tb.erec + 16 * (int64_t)(-1 - se.cfirst);
+                const int2 cc = *reinterpret_cast<const int2*>(rec + 14);
                 se.cfirst = cc.x;
                 se.ccount = cc.y;
             }
