@@ -230,3 +230,26 @@ def test_large_node_with_coincident_core(flags):
     ref = oracle.phase_fof(*arrs, 20.0, lab)
     assert (ref["size"] > 2048).any()
     compare(got, ref)
+
+
+def test_shared_workspace_alternating_calls():
+    # the 3D pass and the 6D level-0 tables share one grow-only workspace:
+    # calls of either kind, on a larger and a smaller input in turn and after
+    # the workspace is released, give the same results
+    big = synth.scaled(synth.CONFIGS["c32"], 300000)
+    small = synth.scaled(synth.CONFIGS["c32"], 20000)
+    ab = [a.cuda() for a in synth.generate(big, 41)]
+    sm = [a.numpy() for a in synth.generate(small, 42)]
+    asm = [torch.from_numpy(a).cuda() for a in sm]
+    lab1, _ = rs.rs_fof3d(*ab[:3], big.box, big.link_len)
+    tree1 = rs.rs_phase_fof_batch(*ab, big.box, lab1)
+    labs, _ = rs.rs_fof3d(*asm[:3], small.box, small.link_len)
+    trees = rs.rs_phase_fof_batch(*asm, small.box, labs)
+    lab2, _ = rs.rs_fof3d(*ab[:3], big.box, big.link_len)
+    rs.rs_release_workspace()
+    tree2 = rs.rs_phase_fof_batch(*ab, big.box, lab2)
+    assert torch.equal(lab1, lab2)
+    _fields_equal(tree1, tree2)
+    ref_lab = oracle.fof3d(*sm[:3], small.box, small.link_len)
+    assert np.array_equal(labs.cpu().numpy(), ref_lab)
+    compare(trees, oracle.phase_fof(*sm, small.box, ref_lab))
