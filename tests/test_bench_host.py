@@ -92,3 +92,11 @@ def test_nn_refinement_dispatches_kept_apart(tmp_path):
     # the batched form has no brackets: every NN dispatch is the exact pass
     rows = {1: (nn, 5.0), 2: ("rs::k_lhist(...)", 0.0), 3: (nn, 7.0)}
     assert bench._kernel_values(rows, "phase_large_nn") == [5.0, 7.0]
+
+
+def test_workload_description_names_the_cube():
+    from paper_2412_18629_amd import synth
+    assert "(512^3)" in bench.workload_description(synth.CONFIGS["c512"])
+    assert "(1024^3)" in bench.workload_description(synth.CONFIGS["c1024"])
+    odd = synth.scaled(synth.CONFIGS["c32"], 1000001)
+    assert "(1000001)" in bench.workload_description(odd)
