@@ -160,10 +160,17 @@ static int64_t lower_key(const kv_t *s, int64_t m, int64_t k)
 /*
  * Periodic cell grid of nc^3 cells whose side L/nc is at least
  * ll (1 + 2^-20) + L 2^-22.  A pair whose computed D <= ll^2 has a computed
- * per-axis |dx| <= ll (1 + 2^-23); the computed difference is within half an
- * ulp of L of the true min-image separation (the image shift itself is exact),
- * so the true separation is below one cell side along every axis and the
- * pair sits in neighbouring cells.  Every such pair is visited.
+ * per-axis |dx| <= ll (1 + 2^-23).  Without an image shift the computed
+ * difference is within 2^-24 (relative) of the true one, so the true
+ * separation stays below ll (1 + 2^-22): the relative term of the margin is
+ * what keeps such a pair in neighbouring cells (a pair on a grid of side
+ * exactly ll, whose difference rounds down onto ll, would otherwise sit two
+ * cells apart).  With an image shift (x_i > x_j across the face) the computed
+ * |dx| = L - fl(x_i - x_j) is at least L - x_i and exceeds x_j, since L - x_i
+ * is a positive multiple of the ulp of x_i, so a pair two cells apart across
+ * the face is never linked.  The absolute term L 2^-22 is further slack (by
+ * itself it is at least three quarters of the relative one, as nc >= 3
+ * below).  Every pair with computed D <= ll^2 is visited.
  */
 int oracle_fof3d(const float *x, const float *y, const float *z,
                  int64_t n, float L, float ll, int32_t *labels)

@@ -133,3 +133,17 @@ def test_repeat_runs_identical():
     a, _ = rs.rs_fof3d(*t, cfg.box, cfg.link_len)
     b, _ = rs.rs_fof3d(*t, cfg.box, cfg.link_len)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L,counts,plain", [(20.0, [57, 100, 333], [0.2875, 0.25]),
+                                            (320.0, [1829, 1000, 257], [0.175, 0.3125]),
+                                            (640.0, [3657], [0.175, 0.625])])
+def test_grid_margin_edge_pairs(L, counts, plain):
+    # pairs at the edge of the linking test across the periodic face and the
+    # cell (and octant) boundaries of the grids next to L / ll, with L / ll
+    # within a few fp32 steps of an integer: the cases the grid margin covers
+    import edge_pairs as ep
+    lls = np.concatenate([ep.near_integer_ratio_lengths(L, counts, 6), np.array(plain, F32)])
+    for ll in lls:
+        pos, _ = ep.edge_pair_box(L, ll, seed=int(float(ll) * 1e6) % 1000)
+        _check(pos, L, ll)

@@ -171,3 +171,35 @@ def test_rejects_out_of_range():
         oracle.fof3d(x, x, np.array([0.0, 4.0], F32), 4.0, 0.2)
     with pytest.raises(oracle.OracleError):
         oracle.fof3d(x, x, np.array([0.0, np.nan], F32), 4.0, 0.2)
+
+
+# Grid margin (cell side >= ll (1 + 2^-20) + L 2^-22): pairs at the edge of
+# the linking test, where a cell grid can miss a pair whose computed D <= ll^2.
+# L / ll lies within two fp32 steps of an integer, so neighbouring cell counts
+# are one rounding apart; pairs straddle the periodic face (where the image
+# shift rounds the separation to the ulp grid of L, linking some pairs whose
+# true separation exceeds ll and separating some within it) and the interior
+# cell boundaries of the grids next to L / ll.  The grid must agree with all
+# pairs (the oracle's own brute path and the independent numpy brute force).
+EDGE_CASES = [(20.0, [57, 100, 333], [0.2875, 0.25]), (320.0, [1829, 1000, 257], [0.175, 0.3125]),
+              (640.0, [3657], [0.175, 0.625]), (100.0, [7, 50], [0.3, 0.78125])]
+
+
+@pytest.mark.parametrize("L,counts,plain", EDGE_CASES)
+def test_grid_margin_edge_pairs(L, counts, plain):
+    import edge_pairs as ep
+    rounded_in = rounded_out = 0
+    lls = np.concatenate([ep.near_integer_ratio_lengths(L, counts, 6), np.array(plain, F32)])
+    for ll in lls:
+        pos, pairs = ep.edge_pair_box(L, ll, seed=int(float(ll) * 1e6) % 1000)
+        x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+        ref = brute.fof3d(x, y, z, L, ll)
+        assert np.array_equal(oracle.fof3d(x, y, z, L, ll), ref), (L, ll)
+        assert np.array_equal(oracle.fof3d(x, y, z, L, ll, brute=True), ref), (L, ll)
+        sep = ep.true_separation(pos, pairs, L)
+        linked = ref[pairs[:, 0]] == ref[pairs[:, 1]]
+        rounded_in += int((linked & (sep > float(ll))).sum())
+        rounded_out += int((~linked & (sep <= float(ll))).sum())
+    # the rounding of the image shift decides some pairs either way: the
+    # construction reaches the cases the margin is about
+    assert rounded_in > 0 or rounded_out > 0
