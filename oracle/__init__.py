@@ -51,6 +51,7 @@ def _load():
     lib.oracle_select_rank.restype = i64
     lib.oracle_node_nn.argtypes = [P, P, P, P, P, P, f32, P, i64, f32, f32, P]
     lib.oracle_node_norm.argtypes = [P, P, P, P, P, P, f32, P, i64, P]
+    lib.oracle_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P]
     _lib = lib
     return lib
 
@@ -146,3 +147,25 @@ def node_norm(x, y, z, vx, vy, vz, box, members):
     out = np.empty(4, np.float32)
     lib.oracle_node_norm(*[_ptr(q) for q in arrs], float(box), _ptr(mem), mem.size, _ptr(out))
     return tuple(float(v) for v in out)
+
+
+PROP_NAMES = ("cx", "cy", "cz", "vx", "vy", "vz", "Mxx", "Myy", "Mzz", "Mxy", "Mxz", "Myz",
+              "jx", "jy", "jz")
+
+
+def halo_props(x, y, z, vx, vy, vz, box, parent, min_index, deepest):
+    """Per-node properties, float32[15, n_nodes] (rows as in PROP_NAMES):
+    centre, bulk velocity, second-moment tensor about the centre and specific
+    angular momentum of the members of each node of a hierarchy."""
+    lib = _load()
+    arrs = [_f32(q) for q in (x, y, z, vx, vy, vz)]
+    par = np.ascontiguousarray(np.asarray(parent, dtype=np.int32))
+    mi = np.ascontiguousarray(np.asarray(min_index, dtype=np.int32))
+    dp = np.ascontiguousarray(np.asarray(deepest, dtype=np.int32))
+    m = par.size
+    out = np.empty((len(PROP_NAMES), m), np.float32)
+    rc = lib.oracle_halo_props(*[_ptr(q) for q in arrs], arrs[0].size, float(box), m, _ptr(par),
+                               _ptr(mi), _ptr(dp), _ptr(out))
+    if rc != 0:
+        raise OracleError(f"oracle_halo_props failed: {rc}")
+    return out

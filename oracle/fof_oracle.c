@@ -751,3 +751,125 @@ int oracle_node_norm(const float *x, const float *y, const float *z,
     out4[0] = r.a; out4[1] = r.c; out4[2] = r.sx2; out4[3] = r.sv2;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* per-node halo properties                                            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Properties of every node of a hierarchy (the halo properties, among them
+ * the inertia tensor, that the paper's Summary lists among the new
+ * functions).  A node's members are the particles whose deepest node is the
+ * node or one of its descendants.  Positions are quantised to 2^-20 and
+ * taken relative to the node's smallest-index member in the nearest periodic
+ * image (as for the dispersions); velocities are quantised to 2^-10.  Per
+ * node, in exact integers:
+ *   S1_a = sum dQ_a, T1_a = sum W_a, S2_ab = sum dQ_a dQ_b,
+ *   A_x = sum (dQ_y W_z - dQ_z W_y) (and cyclic),
+ * then with nn = fl64(N) * fl64(N):
+ *   centre_a   = ((double)Qref_a + (double)S1_a / (double)N) * 2^-20, moved
+ *                into [0, L) by one shift of L in fp64, rounded to fp32 (a
+ *                result equal to L is stored as 0);
+ *   velocity_a = fl32(((double)T1_a / (double)N) * 2^-10);
+ *   M_ab       = fl32((f64(N S2_ab - S1_a S1_b) / nn) * 2^-40), the second
+ *                moment (shape, or inertia) tensor about the centre;
+ *   j_a        = fl32((f64(N A_a - (S1_b T1_c - S1_c T1_b)) / nn) * 2^-30),
+ *                (a, b, c) cyclic: the mean of (x - centre) x (v - velocity),
+ *                the specific angular momentum about the centre.
+ * f64() is the correctly rounded int128 -> fp64 conversion.
+ * Output: props[q * n_nodes + k] for q in
+ *   0..2 centre, 3..5 velocity, 6..11 Mxx Myy Mzz Mxy Mxz Myz, 12..14 j.
+ * Returns 0, -1 (bad argument or inconsistent hierarchy), -3 (memory).
+ */
+int oracle_halo_props(const float *x, const float *y, const float *z,
+                      const float *vx, const float *vy, const float *vz,
+                      int64_t n, float L, int64_t n_nodes, const int32_t *parent,
+                      const int32_t *min_index, const int32_t *deepest, float *props)
+{
+    if (n < 0 || n_nodes < 0 || !(L > 0.0f)) return -1;
+    const float *pc[3] = { x, y, z };
+    const float *vc[3] = { vx, vy, vz };
+    int64_t LQ = (int64_t)rint((double)L * 1048576.0);
+    /* members of each node: walk from each particle's deepest node to the root */
+    int64_t *cnt = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    if (!cnt) return -3;
+    for (int64_t k = 0; k < n_nodes; k++)
+        if (parent[k] >= n_nodes || parent[k] < -1 || min_index[k] < 0 || min_index[k] >= n) {
+            free(cnt);
+            return -1;
+        }
+    for (int64_t i = 0; i < n; i++) {
+        if (deepest[i] < -1 || deepest[i] >= n_nodes) { free(cnt); return -1; }
+        int64_t depth = 0;
+        for (int64_t k = deepest[i]; k >= 0; k = parent[k]) {
+            cnt[k]++;
+            if (++depth > n_nodes) { free(cnt); return -1; }   /* a cycle */
+        }
+    }
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
+    int64_t *fill = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    if (!start || !fill) { free(cnt); free(start); free(fill); return -3; }
+    start[0] = 0;
+    for (int64_t k = 0; k < n_nodes; k++) start[k + 1] = start[k] + cnt[k];
+    int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(start[n_nodes] > 0 ? start[n_nodes] : 1));
+    if (!mem) { free(cnt); free(start); free(fill); return -3; }
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = deepest[i]; k >= 0; k = parent[k]) mem[start[k] + fill[k]++] = i;
+
+    for (int64_t k = 0; k < n_nodes; k++) {
+        int64_t N = cnt[k];
+        const int64_t *m = mem + start[k];
+        int64_t ref = min_index[k];
+        int64_t s1[3] = { 0, 0, 0 }, t1[3] = { 0, 0, 0 }, qref[3];
+        i128 s2[3][3], an[3] = { 0, 0, 0 };
+        for (int a = 0; a < 3; a++) {
+            qref[a] = (int64_t)rint((double)pc[a][ref] * 1048576.0);
+            for (int b = 0; b < 3; b++) s2[a][b] = 0;
+        }
+        for (int64_t t = 0; t < N; t++) {
+            int64_t i = m[t], d[3], w[3];
+            for (int a = 0; a < 3; a++) {
+                d[a] = (int64_t)rint((double)pc[a][i] * 1048576.0) - qref[a];
+                if (2 * d[a] > LQ) d[a] -= LQ;
+                else if (2 * d[a] <= -LQ) d[a] += LQ;
+                w[a] = (int64_t)rint((double)vc[a][i] * 1024.0);
+                s1[a] += d[a];
+                t1[a] += w[a];
+            }
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) s2[a][b] += (i128)d[a] * d[b];
+            for (int a = 0; a < 3; a++) {
+                int b = (a + 1) % 3, c = (a + 2) % 3;
+                an[a] += (i128)d[b] * w[c] - (i128)d[c] * w[b];
+            }
+        }
+        float out[15];
+        if (N == 0) {
+            for (int q = 0; q < 15; q++) out[q] = 0.0f;
+        } else {
+            double nn = (double)N * (double)N;
+            for (int a = 0; a < 3; a++) {
+                double u = ((double)qref[a] + (double)s1[a] / (double)N) * 9.5367431640625e-07;
+                if (u < 0.0) u += (double)L;
+                else if (u >= (double)L) u -= (double)L;
+                float c = (float)u;
+                out[a] = (c >= L) ? 0.0f : c;
+                out[3 + a] = (float)(((double)t1[a] / (double)N) * 9.765625e-4);
+            }
+            static const int pa[6] = { 0, 1, 2, 0, 0, 1 }, pb[6] = { 0, 1, 2, 1, 2, 2 };
+            for (int q = 0; q < 6; q++) {
+                int a = pa[q], b = pb[q];
+                i128 cm = (i128)N * s2[a][b] - (i128)s1[a] * s1[b];
+                out[6 + q] = (float)(((double)cm / nn) * 9.094947017729282e-13);   /* 2^-40 */
+            }
+            for (int a = 0; a < 3; a++) {
+                int b = (a + 1) % 3, c = (a + 2) % 3;
+                i128 jn = (i128)N * an[a] - ((i128)s1[b] * t1[c] - (i128)s1[c] * t1[b]);
+                out[12 + a] = (float)(((double)jn / nn) * 9.313225746154785e-10);  /* 2^-30 */
+            }
+        }
+        for (int q = 0; q < 15; q++) props[q * n_nodes + k] = out[q];
+    }
+    free(cnt); free(start); free(fill); free(mem);
+    return 0;
+}

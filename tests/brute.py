@@ -155,3 +155,52 @@ def phase_fof(x, y, z, vx, vy, vz, L, labels, min_group=10, min_sub=10, f=0.7):
         d["parent"] = -1 if d["parent_key"] is None else index[d["parent_key"]]
         deepest[d["members"]] = i
     return nodes, deepest
+
+
+def exact_props(pos, vel, L, ref=0):
+    """Centre, bulk velocity, second-moment tensor about the centre and mean
+    (x - centre) x (v - velocity) of one member set, as exact Fractions.
+
+    Positions are quantised to 2^-20 (round half even in fp64) and moved to
+    the nearest periodic image of member `ref` in integers; velocities are
+    quantised to 2^-10.  The centre is returned in [0, L) (exact rational, in
+    Mpc/h); the tensor rows are xx, yy, zz, xy, xz, yz.
+    """
+    n = pos.shape[0]
+    LQ = int(np.rint(np.float64(L) * 2.0 ** 20))
+    d = np.zeros((n, 3), dtype=object)
+    w = np.zeros((n, 3), dtype=object)
+    qref = [int(v) for v in np.rint(pos[ref].astype(np.float64) * 2.0 ** 20)]
+    for ax in range(3):
+        q = [int(v) for v in np.rint(pos[:, ax].astype(np.float64) * 2.0 ** 20)]
+        for i in range(n):
+            t = q[i] - qref[ax]
+            if 2 * t > LQ:
+                t -= LQ
+            elif 2 * t <= -LQ:
+                t += LQ
+            d[i, ax] = t
+            w[i, ax] = int(np.rint(np.float64(vel[i, ax]) * 2.0 ** 10))
+    mean_d = [Fraction(sum(d[:, a]), n) for a in range(3)]
+    mean_w = [Fraction(sum(w[:, a]), n) for a in range(3)]
+    cen = []
+    Lf = Fraction(float(L))
+    for a in range(3):
+        c = (qref[a] + mean_d[a]) / 2 ** 20
+        if c < 0:
+            c += Lf
+        elif c >= Lf:
+            c -= Lf
+        cen.append(c)
+    vbar = [m / 2 ** 10 for m in mean_w]
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    M = [sum((Fraction(d[i, a]) - mean_d[a]) * (Fraction(d[i, b]) - mean_d[b])
+             for i in range(n)) / n / 2 ** 40 for a, b in pairs]
+    j = []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        s = sum((Fraction(d[i, b]) - mean_d[b]) * (Fraction(w[i, c]) - mean_w[c]) -
+                (Fraction(d[i, c]) - mean_d[c]) * (Fraction(w[i, b]) - mean_w[b])
+                for i in range(n))
+        j.append(s / n / 2 ** 30)
+    return cen + vbar + M + j
