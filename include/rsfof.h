@@ -152,6 +152,52 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z,
                        void* stream);
 
 /*
+ * rs_halo_props -- per-node halo properties over a hierarchy returned by
+ * rs_phase_fof_batch (the halo properties, inertia tensor among them, that
+ * the paper's Summary lists among MPI-Rockstar's new functions).
+ *
+ * A node's members are the particles whose deepest node is the node or one
+ * of its descendants.  Positions are quantised to 2^-20 and taken relative
+ * to the node's smallest-index member (min_index) in the nearest periodic
+ * image, velocities quantised to 2^-10; all sums are exact integers, so the
+ * result does not depend on member order.  Per node (N members):
+ *   centre   ((double)Q_ref + (double)sum(dQ) / N) * 2^-20 (fp64), moved into
+ *            [0, box) by one shift of box, rounded to fp32 (box is stored as 0);
+ *   velocity fl32(((double)sum(W) / N) * 2^-10), the bulk velocity;
+ *   M_ab     fl32((f64(N sum(dQ_a dQ_b) - sum(dQ_a) sum(dQ_b)) / (N N)) * 2^-40),
+ *            the second-moment (shape, inertia) tensor about the centre;
+ *   j_a      fl32((f64(N sum(dQ_b W_c - dQ_c W_b) - (sum(dQ_b) sum(W_c) -
+ *            sum(dQ_c) sum(W_b))) / (N N)) * 2^-30), (a, b, c) cyclic: the mean
+ *            of (x - centre) x (v - velocity), the specific angular momentum.
+ *
+ *   x..vz       [n] fp32 positions (0 <= x < box) and velocities (|v| < 2^20).
+ *   box         periodic box side, 0 < box < 2048 (quantised coordinates and
+ *               their 128-bit moments stay exact below that).
+ *   n_nodes, n_levels, level, parent, min_index, size, deepest: the hierarchy
+ *               exactly as rs_tree holds it (canonical order; deepest [n]).
+ *   props       [RS_NPROP * n_nodes] fp32 output, caller-allocated, row-major
+ *               by property: props[q * n_nodes + k], q in RS_PROP_* order.
+ * The hierarchy is checked on the device (levels sorted, each parent one
+ * level up and earlier, child sizes within the parent, every node's own
+ * particles exactly size minus its children's sizes): RS_EINVAL otherwise,
+ * before any output is written.  Uses the library's workspace; returns after
+ * synchronising `stream`.  RS_OK, RS_EINVAL, RS_ERANGE, RS_ENOMEM, RS_EDEVICE.
+ */
+enum {
+    RS_PROP_CX = 0, RS_PROP_CY, RS_PROP_CZ,        /* centre */
+    RS_PROP_VX, RS_PROP_VY, RS_PROP_VZ,            /* bulk velocity */
+    RS_PROP_MXX, RS_PROP_MYY, RS_PROP_MZZ,         /* second-moment tensor */
+    RS_PROP_MXY, RS_PROP_MXZ, RS_PROP_MYZ,
+    RS_PROP_JX, RS_PROP_JY, RS_PROP_JZ,            /* specific angular momentum */
+    RS_NPROP
+};
+int rs_halo_props(const float* x, const float* y, const float* z, const float* vx,
+                  const float* vy, const float* vz, int64_t n, float box, int64_t n_nodes,
+                  int64_t n_levels, const int32_t* level, const int32_t* parent,
+                  const int32_t* min_index, const int32_t* size, const int32_t* deepest,
+                  float* props, void* stream);
+
+/*
  * Linking-length proposer: a small network that predicts ln l of a node from
  * 24 summary features.  It never decides a result: RS_LEARNED verifies every
  * proposal exactly and completes rejected ones with the exact search.  All
@@ -182,7 +228,7 @@ int rs_mlp_infer(const float* model, int64_t n, const float* features, float* ou
  * Instrumentation (not part of the method).  While enabled, the library
  * records HIP events on the launching stream around its main kernels
  * ("fof3d_link", "phase_small", "phase_large_nn", "phase_large_link",
- * "phase_large_nn_fallback") and
+ * "phase_large_nn_fallback", "halo_props") and
  * accumulates their elapsed time, launch count and processed work units
  * (particles or node members).  rs_profile_enable(0) clears the records.
  * rs_profile_get synchronises on the recorded events; unknown names report

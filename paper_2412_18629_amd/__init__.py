@@ -25,7 +25,7 @@ EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_vers
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
             "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
             "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_tune_set", "rs_tune_get",
-            "rs_tune_name")
+            "rs_tune_name", "rs_halo_props")
 
 
 class RsError(RuntimeError):
@@ -80,6 +80,7 @@ def load():
     lib.rs_mlp_standardize.argtypes = [P, i64, P, P, ctypes.c_int, P]
     lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
     lib.rs_sort_pairs_u64_i32.argtypes = [P, P, P, P, i64, ctypes.c_int, P]
+    lib.rs_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, i64, P, P, P, P, P, P, P]
     lib.rs_release_workspace.argtypes = []
     lib.rs_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int]
     lib.rs_tune_set.restype = ctypes.c_int
@@ -89,7 +90,7 @@ def load():
     lib.rs_tune_name.argtypes = [ctypes.c_int]
     lib.rs_tune_name.restype = ctypes.c_char_p
     for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
-               "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace"):
+               "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_halo_props"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -254,6 +255,41 @@ def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_s
     finally:
         lib.rs_free(out)
     return res
+
+
+PROP_NAMES = ("cx", "cy", "cz", "vx", "vy", "vz", "Mxx", "Myy", "Mzz", "Mxy", "Mxz", "Myz",
+              "jx", "jy", "jz")
+RS_NPROP = len(PROP_NAMES)
+
+
+def rs_halo_props(x, y, z, vx, vy, vz, box, tree, out=None, stream=None):
+    """Per-node halo properties of a hierarchy (the dict rs_phase_fof_batch
+    returns): float32 device tensor [RS_NPROP, n_nodes], rows as in
+    PROP_NAMES (centre, bulk velocity, second-moment tensor, specific angular
+    momentum)."""
+    lib = load()
+    n = x.numel()
+    arrs = (x, y, z, vx, vy, vz)
+    names = ("x", "y", "z", "vx", "vy", "vz")
+    for t, nm in zip(arrs, names):
+        if t.numel() != n:
+            raise ValueError(f"{nm} size differs from x")
+    m = tree["level"].numel()
+    for k in ("parent", "min_index", "size"):
+        if tree[k].numel() != m:
+            raise ValueError(f"tree field {k} has the wrong size")
+    if tree["deepest"].numel() != n:
+        raise ValueError("tree field deepest has the wrong size")
+    if out is None:
+        out = torch.empty((RS_NPROP, m), dtype=torch.float32, device=x.device)
+    if out.shape != (RS_NPROP, m):
+        raise ValueError("out has the wrong shape")
+    ptrs = [_dev(t, torch.float32, nm) for t, nm in zip(arrs, names)]
+    tp = [_dev(tree[k], torch.int32, k) for k in ("level", "parent", "min_index", "size",
+                                                  "deepest")]
+    _ck(lib.rs_halo_props(*ptrs, n, float(box), m, int(tree["n_levels"]), *tp,
+                          _dev(out, torch.float32, "out"), _stream(stream)), "rs_halo_props")
+    return out
 
 
 def rs_profile_enable(on: bool = True) -> None:

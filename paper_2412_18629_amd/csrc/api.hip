@@ -13,6 +13,10 @@ int phase_run(const float* x, const float* y, const float* z, const float* vx,
               int32_t min_group, int32_t min_sub, double f, uint32_t flags, const void* model,
               rs_tree** out, hipStream_t st);
 void tree_release(rs_tree* t);
+int props_run(const float* x, const float* y, const float* z, const float* vx,
+              const float* vy, const float* vz, int64_t n, float L, int64_t m, int64_t nlev,
+              const int32_t* level, const int32_t* parent, const int32_t* min_index,
+              const int32_t* size, const int32_t* deepest, float* props, hipStream_t st);
 
 static int device_ready() {
     int cnt = 0;
@@ -60,6 +64,26 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
                                 (1u << rs::AR_TREE) | (1u << rs::AR_MLP)));
     return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,
                          model, out, static_cast<hipStream_t>(stream));
+}
+
+int rs_halo_props(const float* x, const float* y, const float* z, const float* vx,
+                  const float* vy, const float* vz, int64_t n, float box, int64_t n_nodes,
+                  int64_t n_levels, const int32_t* level, const int32_t* parent,
+                  const int32_t* min_index, const int32_t* size, const int32_t* deepest,
+                  float* props, void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31) return RS_EINVAL;
+    if (n_nodes < 0 || n_nodes >= (int64_t)1 << 31) return RS_EINVAL;
+    if (n_levels < 0 || n_levels > n_nodes) return RS_EINVAL;
+    if (n_nodes > 0 && n_levels < 1) return RS_EINVAL;
+    if (!(box > 0.0f) || !(box < 2048.0f)) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !deepest)) return RS_EINVAL;
+    if (n_nodes > 0 && (!level || !parent || !min_index || !size || !props)) return RS_EINVAL;
+    if (n == 0 && n_nodes > 0) return RS_EINVAL;   /* nodes without particles */
+    RS_TRY(rs::device_ready());
+    if (n == 0) return RS_OK;
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
+    return rs::props_run(x, y, z, vx, vy, vz, n, box, n_nodes, n_levels, level, parent,
+                         min_index, size, deepest, props, static_cast<hipStream_t>(stream));
 }
 
 int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int32_t* vals_in,

@@ -105,3 +105,15 @@ def test_tuning_table_rejects_unknown_knobs_and_values():
     lib = rs.load()
     assert lib.rs_tune_set(b"no_such_knob", 1) == rs.RS_EINVAL
     assert lib.rs_tune_set(b"xcd_chunk", 3) == rs.RS_EINVAL
+
+
+@pytest.mark.parametrize("n,box,m,nlev", [(10, 2048.0, 1, 1), (10, 0.0, 1, 1), (-1, 10.0, 1, 1),
+                                          (10, 10.0, 1, 2), (10, 10.0, 1, 0), (10, 10.0, -1, 0),
+                                          (0, 10.0, 1, 1)])
+def test_halo_props_rejects_bad_arguments_before_device_work(n, box, m, nlev):
+    lib = rs.load()
+    p = ctypes.c_void_p(1)
+    rc = lib.rs_halo_props(p, p, p, p, p, p, n, box, m, nlev, p, p, p, p, p, p, None)
+    if rc == rs.RS_EDEVICE:
+        pytest.skip("argument check passed; no device here")
+    assert rc == rs.RS_EINVAL
