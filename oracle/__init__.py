@@ -52,6 +52,7 @@ def _load():
     lib.oracle_node_nn.argtypes = [P, P, P, P, P, P, f32, P, i64, f32, f32, P]
     lib.oracle_node_norm.argtypes = [P, P, P, P, P, P, f32, P, i64, P]
     lib.oracle_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P]
+    lib.oracle_fof3d_subbox.argtypes = [P, P, P, i64, i64, P, P, f32, f32, ctypes.c_int, P]
     _lib = lib
     return lib
 
@@ -79,6 +80,27 @@ def fof3d(x, y, z, box, link_len, brute=False):
     if rc != 0:
         raise OracleError(f"oracle_fof3d failed: {rc}")
     return lab
+
+
+def fof3d_subbox(x, y, z, n_owned, lo, hi, ghost_width, link_len, brute=False):
+    """3D FoF over a non-periodic sub-box [lo, hi) whose particles [0, n_owned)
+    are owned and the rest are ghosts within ghost_width of it.  Returns
+    (labels, ghost_links): labels = smallest member index per group; the
+    ghost links are the (ghost index, label) pairs of the ghosts whose group
+    holds an owned particle (label < n_owned), by ghost index."""
+    lib = _load()
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.size
+    lab = np.empty(n, dtype=np.int32)
+    lo3, hi3 = _f32(lo), _f32(hi)
+    rc = lib.oracle_fof3d_subbox(_ptr(x), _ptr(y), _ptr(z), n, int(n_owned), _ptr(lo3),
+                                 _ptr(hi3), float(ghost_width), float(link_len),
+                                 1 if brute else 0, _ptr(lab))
+    if rc != 0:
+        raise OracleError(f"oracle_fof3d_subbox failed: {rc}")
+    g = np.arange(int(n_owned), n, dtype=np.int32)
+    keep = lab[g] < int(n_owned)
+    return lab, np.stack([g[keep], lab[g][keep]], 1).astype(np.int32)
 
 
 NODE_FIELDS = ("level", "min_index", "parent", "size", "l2", "a", "c", "sx2", "sv2", "wide")

@@ -226,6 +226,118 @@ int oracle_fof3d(const float *x, const float *y, const float *z,
 }
 
 /* ------------------------------------------------------------------ */
+/* 3D FoF over a non-periodic sub-box with a ghost shell                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The per-process FoF of the paper's decomposition (Parallelization
+ * section): a process holds the particles of its sub-box [lo, hi) (owned,
+ * indices [0, n_owned)) plus ghost copies of other processes' particles
+ * within the shell [lo - gw, hi + gw) (indices [n_owned, n)).  No periodic
+ * shift: D = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)) with dx = fl(xi - xj).
+ * Labels are the smallest member index of each group.  Positions outside
+ * their region (or non-finite) return -2.
+ *
+ * brute != 0 tests all pairs; otherwise a cell grid over the shell's
+ * bounding cube with side >= ll (1 + 2^-20) + E 2^-22 (E the cube's side)
+ * visits every pair in neighbouring cells (the margin argument of the
+ * periodic grid, without the face).
+ */
+static int check_subbox(const float *x, const float *y, const float *z, int64_t n,
+                        int64_t n_owned, const float *lo, const float *hi, float gw)
+{
+    const float *pc[3] = { x, y, z };
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            float v = pc[a][i];
+            if (i < n_owned) {
+                if (!(v >= lo[a] && v < hi[a])) return -2;
+            } else {
+                double d = (double)v;
+                if (!(d >= (double)lo[a] - (double)gw && d < (double)hi[a] + (double)gw)) return -2;
+            }
+        }
+    return 0;
+}
+
+static float pos_d2_open(const float *x, const float *y, const float *z, int64_t i, int64_t j)
+{
+    float dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+    float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+    float t = sx + sy;
+    return t + sz;
+}
+
+int oracle_fof3d_subbox(const float *x, const float *y, const float *z, int64_t n,
+                        int64_t n_owned, const float *lo, const float *hi, float gw, float ll,
+                        int brute, int32_t *labels)
+{
+    if (n < 0 || n_owned < 0 || n_owned > n || !(ll > 0.0f) || !(gw >= 0.0f)) return -1;
+    for (int a = 0; a < 3; a++)
+        if (!(hi[a] > lo[a])) return -1;
+    if (check_subbox(x, y, z, n, n_owned, lo, hi, gw)) return -2;
+    float ll2 = ll * ll;
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!parent) return -3;
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
+    double o[3], E = 0.0;
+    for (int a = 0; a < 3; a++) {
+        o[a] = (double)lo[a] - (double)gw;
+        double e = ((double)hi[a] + (double)gw) - o[a];
+        if (e > E) E = e;
+    }
+    double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + E * ldexp(1.0, -22);
+    int64_t nc = (int64_t)floor(E / side_min);
+    if (brute || nc < 3 || nc > 2000000) {
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = i + 1; j < n; j++)
+                if (pos_d2_open(x, y, z, i, j) <= ll2) uf_union(parent, i, j);
+    } else {
+        double scale = (double)nc / E;
+        const float *pc[3] = { x, y, z };
+        kv_t *s = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+        if (!s) { free(parent); return -3; }
+        for (int64_t i = 0; i < n; i++) {
+            int64_t c[3];
+            for (int a = 0; a < 3; a++) {
+                c[a] = (int64_t)floor(((double)pc[a][i] - o[a]) * scale);
+                if (c[a] >= nc) c[a] = nc - 1;
+                if (c[a] < 0) c[a] = 0;
+            }
+            s[i].key = (c[2] * nc + c[1]) * nc + c[0];
+            s[i].idx = i;
+        }
+        qsort(s, (size_t)n, sizeof(kv_t), cmp_kv);
+        int64_t start = 0;
+        while (start < n) {
+            int64_t key = s[start].key, end = start;
+            while (end < n && s[end].key == key) end++;
+            int64_t cx = key % nc, cy = (key / nc) % nc, cz = key / (nc * nc);
+            for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int64_t ox = cx + dx, oy = cy + dy, oz = cz + dz;
+                if (ox < 0 || oy < 0 || oz < 0 || ox >= nc || oy >= nc || oz >= nc) continue;
+                int64_t nk = (oz * nc + oy) * nc + ox;
+                if (nk < key) continue;          /* each cell pair once */
+                int64_t b0 = lower_key(s, n, nk);
+                for (int64_t p = start; p < end; p++)
+                    for (int64_t q = b0; q < n && s[q].key == nk; q++) {
+                        if (nk == key && q <= p) continue;
+                        if (pos_d2_open(x, y, z, s[p].idx, s[q].idx) <= ll2)
+                            uf_union(parent, s[p].idx, s[q].idx);
+                    }
+            }
+            start = end;
+        }
+        free(s);
+    }
+    for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
+    free(parent);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* exact integer moments -> dispersions and metric factors             */
 /* ------------------------------------------------------------------ */
 
