@@ -84,6 +84,38 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n,
              void* stream);
 
 /*
+ * rs_fof3d_subbox -- 3D friends-of-friends over one process's non-periodic
+ * sub-box with a ghost shell (the paper's decomposition, Parallelization
+ * section: each process runs the 3D FoF over its own sub-box, and halos are
+ * then joined across processes through the particles near the boundaries).
+ *
+ * Particles [0, n_owned) are the process's own and lie in [lo, hi) per
+ * axis; particles [n_owned, n) are ghost copies of other processes'
+ * particles (periodic images shifted into this frame, as the caller
+ * decomposes the box) in the shell [lo - ghost_width, hi + ghost_width).
+ * Groups are the connected components of D(i,j) <= link_len^2 over all n
+ * particles, with the pair arithmetic of rs_fof3d WITHOUT the periodic
+ * shift.  For the union across processes to find every link, ghost_width
+ * must exceed link_len (by any margin above 2^-20 relative).
+ *   lo, hi       (host) float[3], lo < hi.
+ *   ghost_width  >= 0.
+ *   link_len     > 0.
+ *   labels       [n] int32 output: the smallest index (in this call's
+ *                numbering) of each particle's group.
+ *   ghost_links  [2 * (n - n_owned)] int32 output or NULL: pairs
+ *                (ghost index, its label) for every ghost whose group holds
+ *                an owned particle (label < n_owned), by ghost index; the
+ *                cross-process union joins the ghost's own process's group
+ *                with this one through them.
+ *   n_links      (host) number of pairs; required with ghost_links.
+ * Positions outside their region or not finite: RS_ERANGE.  Synchronous with
+ * respect to `stream` on return.
+ */
+int rs_fof3d_subbox(const float* x, const float* y, const float* z, int64_t n, int64_t n_owned,
+                    const float* lo, const float* hi, float ghost_width, float link_len,
+                    int32_t* labels, int32_t* ghost_links, int64_t* n_links, void* stream);
+
+/*
  * Node hierarchy returned by rs_phase_fof_batch.  The struct lives in host
  * memory; every array lives in ONE library-owned device allocation, released
  * only by rs_free.

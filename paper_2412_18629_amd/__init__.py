@@ -25,7 +25,7 @@ EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_vers
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
             "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
             "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_tune_set", "rs_tune_get",
-            "rs_tune_name", "rs_halo_props")
+            "rs_tune_name", "rs_halo_props", "rs_fof3d_subbox")
 
 
 class RsError(RuntimeError):
@@ -60,6 +60,9 @@ def load():
                                   ctypes.c_float, ctypes.c_double, ctypes.c_uint32)
     lib.rs_fof3d.argtypes = [P, P, P, i64, f32, f32, P, ctypes.POINTER(i64), P]
     lib.rs_fof3d.restype = ctypes.c_int
+    lib.rs_fof3d_subbox.argtypes = [P, P, P, i64, i64, P, P, f32, f32, P, P,
+                                    ctypes.POINTER(i64), P]
+    lib.rs_fof3d_subbox.restype = ctypes.c_int
     lib.rs_phase_fof_batch.argtypes = [P, P, P, P, P, P, i64, f32, P, i32, i32, f64, u32, P,
                                        ctypes.POINTER(ctypes.POINTER(_Tree)), P]
     lib.rs_phase_fof_batch.restype = ctypes.c_int
@@ -135,6 +138,37 @@ def rs_fof3d(x, y, z, box, link_len, labels=None, stream=None):
     if rc != RS_OK:
         raise RsError(rc, "rs_fof3d")
     return labels, int(ng.value)
+
+
+def rs_fof3d_subbox(x, y, z, n_owned, lo, hi, ghost_width, link_len, labels=None,
+                    links=True, stream=None):
+    """3D FoF over a non-periodic sub-box [lo, hi) with owned particles
+    [0, n_owned) and ghosts after them.  Returns (labels, ghost_links): int32
+    device tensors, ghost_links of shape (n_links, 2) holding (ghost index,
+    label) for the ghosts whose group holds an owned particle (None when
+    links is False)."""
+    lib = load()
+    n = x.numel()
+    for t, nm in ((y, "y"), (z, "z")):
+        if t.numel() != n:
+            raise ValueError(f"{nm} size differs from x")
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=x.device)
+    lo3 = (ctypes.c_float * 3)(*[float(v) for v in lo])
+    hi3 = (ctypes.c_float * 3)(*[float(v) for v in hi])
+    ng = max(n - int(n_owned), 0)
+    buf = torch.empty(max(2 * ng, 2), dtype=torch.int32, device=x.device) if links else None
+    cnt = ctypes.c_int64(-1)
+    ptrs = [_dev(t, torch.float32, nm) for t, nm in ((x, "x"), (y, "y"), (z, "z"))]
+    rc = lib.rs_fof3d_subbox(*ptrs, n, int(n_owned), lo3, hi3, float(ghost_width),
+                             float(link_len), _dev(labels, torch.int32, "labels"),
+                             _dev(buf, torch.int32, "ghost_links") if links else None,
+                             ctypes.byref(cnt) if links else None, _stream(stream))
+    if rc != RS_OK:
+        raise RsError(rc, "rs_fof3d_subbox")
+    if not links:
+        return labels, None
+    return labels, buf[: 2 * int(cnt.value)].view(-1, 2)
 
 
 def rs_sort_pairs(keys, vals, bits=64, stream=None):

@@ -8,6 +8,9 @@
 namespace rs {
 int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
               int32_t* labels, int64_t* n_groups, hipStream_t st);
+int fof3d_subbox_run(const float* x, const float* y, const float* z, int64_t n,
+                     int64_t n_owned, const float* lo, const float* hi, float gw, float ll,
+                     int32_t* labels, int32_t* ghost_links, int64_t* n_links, hipStream_t st);
 int phase_run(const float* x, const float* y, const float* z, const float* vx,
               const float* vy, const float* vz, int64_t n, float L, const int32_t* labels,
               int32_t min_group, int32_t min_sub, double f, uint32_t flags, const void* model,
@@ -45,6 +48,27 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float bo
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
                          static_cast<hipStream_t>(stream));
+}
+
+int rs_fof3d_subbox(const float* x, const float* y, const float* z, int64_t n, int64_t n_owned,
+                    const float* lo, const float* hi, float ghost_width, float link_len,
+                    int32_t* labels, int32_t* ghost_links, int64_t* n_links, void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31 || n_owned < 0 || n_owned > n) return RS_EINVAL;
+    if (!lo || !hi) return RS_EINVAL;
+    for (int a = 0; a < 3; a++)
+        if (!isfinite(lo[a]) || !isfinite(hi[a]) || !(hi[a] > lo[a])) return RS_EINVAL;
+    if (!(ghost_width >= 0.0f) || !isfinite(ghost_width)) return RS_EINVAL;
+    if (!(link_len > 0.0f) || !isfinite(link_len)) return RS_EINVAL;
+    if (ghost_links && !n_links) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !labels)) return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    if (n == 0) {
+        if (n_links) *n_links = 0;
+        return RS_OK;
+    }
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
+    return rs::fof3d_subbox_run(x, y, z, n, n_owned, lo, hi, ghost_width, link_len, labels,
+                                ghost_links, n_links, static_cast<hipStream_t>(stream));
 }
 
 int rs_phase_fof_batch(const float* x, const float* y, const float* z, const float* vx,

@@ -33,11 +33,22 @@ namespace rs {
 
 struct Grid3 {
     int64_t nc;        // cells per axis
-    double scale;      // nc / L (fp64)
-    float L, h, ll2;
+    double scale;      // nc / E (fp64), E the side of the gridded cube
+    double o[3];       // corner of the gridded cube (0 for a periodic box)
+    float L, h, ll2;   // periodic box side and half side (periodic grids only)
     int key_bits;
     bool autolink;     // every octant pair closer than ll
-    bool octfilter;    // octant offsets of 3 half-cells cannot link (nc >= 3)
+    bool octfilter;    // octant offsets of 3 half-cells cannot link (no wrap, or nc >= 3)
+};
+
+// where the particles must lie: a periodic box [0, L), or a sub-box whose
+// owned particles [0, n_owned) lie in [lo, hi) and ghosts in the shell
+// [lo - gw, hi + gw) (bounds of the shell in fp64)
+struct Bounds {
+    bool periodic;
+    int64_t n_owned;
+    float lo[3], hi[3];
+    double glo[3], ghi[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -45,7 +56,7 @@ struct Grid3 {
 // ---------------------------------------------------------------------------
 
 __global__ void k_keys(const float* __restrict__ x, const float* __restrict__ y,
-                       const float* __restrict__ z, int64_t n, Grid3 g,
+                       const float* __restrict__ z, int64_t n, Grid3 g, Bounds B,
                        uint64_t* __restrict__ keys, int32_t* __restrict__ idx,
                        int32_t* __restrict__ err) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -56,8 +67,10 @@ __global__ void k_keys(const float* __restrict__ x, const float* __restrict__ y,
     bool bad = false;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        bad |= !(p[a] >= 0.0f && p[a] < g.L);
-        double u = (double)p[a] * g.scale;
+        if (B.periodic) bad |= !(p[a] >= 0.0f && p[a] < g.L);
+        else if (i < B.n_owned) bad |= !(p[a] >= B.lo[a] && p[a] < B.hi[a]);
+        else bad |= !((double)p[a] >= B.glo[a] && (double)p[a] < B.ghi[a]);
+        double u = ((double)p[a] - g.o[a]) * g.scale;
         int64_t ci = (int64_t)floor(u);
         int64_t oi = (int64_t)floor(2.0 * u) - 2 * ci;
         if (ci >= g.nc) { ci = g.nc - 1; oi = 1; }
@@ -181,7 +194,15 @@ RS_DEV void row_cells(const LinkArgs& A, uint64_t rr, int32_t& b, int32_t& e) {
 // is a short walk, and it is updated to the current root on every use.  With
 // auto-link the union-find runs over octant indices (one element per octant,
 // a dense array half the size of the slot array); otherwise over slots.
-template <bool AUTOLINK>
+// pair distance with the periodic shift (PER) or without (sub-box)
+template <bool PER>
+RS_DEV float link_d2(float xi, float yi, float zi, float xj, float yj, float zj,
+                     const Grid3& g) {
+    return PER ? pos_d2_wrap(xi, yi, zi, xj, yj, zj, g.L, g.h)
+               : pos_d2_nowrap(xi, yi, zi, xj, yj, zj);
+}
+
+template <bool AUTOLINK, bool PER>
 RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int oa, int32_t c,
                       int dx, int dy, int dz, int32_t& ra) {
     const Grid3& g = A.g;
@@ -212,7 +233,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             for (int32_t i = s0; i < s1 && !hit; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
                 for (int32_t j = t0; j < t1; j++) {
-                    if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2) {
+                    if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2) {
                         hit = true;
                         break;
                     }
@@ -224,7 +245,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             for (int32_t i = s0; i < s1; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
                 for (int32_t j = t0; j < t1; j++)
-                    if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2)
+                    if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2)
                         uf_unite(A.parent, i, j);
             }
         }
@@ -235,7 +256,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
 // 27-cell neighbourhood.  Octants are numbered in cell-key order, so cells
 // with a smaller key (among them every cell of an earlier row) hold only
 // earlier octants, whose pairs with this one are taken from their side.
-template <bool AUTOLINK>
+template <bool AUTOLINK, bool PER>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_link(LinkArgs A) {
     const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= A.n_oct) return;
@@ -253,7 +274,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         for (int32_t i = s0; i < s1; i++) {
             const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
             for (int32_t j = i + 1; j < s1; j++)
-                if (pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g.L, g.h) <= g.ll2)
+                if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2)
                     uf_unite(A.parent, i, j);
         }
     }
@@ -262,9 +283,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const bool inner = nc >= 3 && cx >= 1 && cx <= nc - 2;
     for (int dz = -1; dz <= 1; dz++) {
         int64_t nz = cz + dz;
+        if (!PER && (nz < 0 || nz >= nc)) continue;
         nz = nz < 0 ? nz + nc : (nz >= nc ? nz - nc : nz);
         for (int dy = -1; dy <= 1; dy++) {
             int64_t ny = cy + dy;
+            if (!PER && (ny < 0 || ny >= nc)) continue;
             ny = ny < 0 ? ny + nc : (ny >= nc ? ny - nc : ny);
             const uint64_t rr = (uint64_t)(nz * nc + ny);
             if (rr < row) continue;
@@ -278,18 +301,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                     const uint64_t nkey = A.cell_key[c];
                     if (nkey > khi) break;
                     if (nkey < cell) continue;
-                    link_cell<AUTOLINK>(A, a, s0, s1, oa, c, (int)(nkey - klo) - 1, dy, dz,
-                                        ra);
+                    link_cell<AUTOLINK, PER>(A, a, s0, s1, oa, c, (int)(nkey - klo) - 1, dy,
+                                             dz, ra);
                 }
             } else {
                 for (int dx = -1; dx <= 1; dx++) {
                     int64_t nx = cx + dx;
+                    if (!PER && (nx < 0 || nx >= nc)) continue;
                     nx = nx < 0 ? nx + nc : (nx >= nc ? nx - nc : nx);
                     const uint64_t nkey = rbase + (uint64_t)nx;
                     if (nkey < cell) continue;
                     const int32_t c = lower_bound_u64(A.cell_key, rb, re, nkey);
                     if (c < re && A.cell_key[c] == nkey)
-                        link_cell<AUTOLINK>(A, a, s0, s1, oa, c, dx, dy, dz, ra);
+                        link_cell<AUTOLINK, PER>(A, a, s0, s1, oa, c, dx, dy, dz, ra);
                 }
             }
         }
@@ -305,6 +329,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 // at a time until the first one within ll
 constexpr int HEAVY_BLOCKS = 8192;
 
+template <bool PER>
 __global__ void __launch_bounds__(64) k_link_heavy(LinkArgs A) {
     const int lane = threadIdx.x;
     const int32_t nq = min(*A.n_heavy, A.cap_heavy);
@@ -320,8 +345,8 @@ __global__ void __launch_bounds__(64) k_link_heavy(LinkArgs A) {
             const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
             for (int32_t j0 = t0; j0 < t1 && !hit; j0 += 64) {
                 const int32_t j = j0 + lane;
-                const bool near = j < t1 && pos_d2_wrap(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j],
-                                                        g.L, g.h) <= g.ll2;
+                const bool near = j < t1 && link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j],
+                                                         A.sz[j], g) <= g.ll2;
                 hit = __ballot(near) != 0;
             }
         }
@@ -395,13 +420,19 @@ k_write_labels(int64_t n, const int32_t* __restrict__ parent, const int32_t* __r
 // host driver
 // ---------------------------------------------------------------------------
 
-static int plan_grid(float L, float ll, Grid3* g) {
-    double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + (double)L * ldexp(1.0, -22);
-    int64_t nc = (int64_t)floor((double)L / side_min);
+// Cell grid over the cube of side E with corner o: cells of side at least
+// ll (1 + 2^-20) + E 2^-22, so every pair whose computed D <= ll^2 lies in
+// neighbouring cells (the relative term covers the rounding of an unshifted
+// difference; across a periodic face the computed difference is never below
+// either particle's distance to the face; the absolute term is slack).
+static int plan_grid(double E, float ll, bool periodic, const double o[3], float L, Grid3* g) {
+    double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + E * ldexp(1.0, -22);
+    int64_t nc = (int64_t)floor(E / side_min);
     if (nc < 1) nc = 1;
     if (nc > (1 << 20)) return RS_EINVAL;
     g->nc = nc;
-    g->scale = (double)nc / (double)L;
+    g->scale = (double)nc / E;
+    for (int a = 0; a < 3; a++) g->o[a] = o[a];
     g->L = L;
     g->h = 0.5f * L;
     g->ll2 = ll * ll;
@@ -409,21 +440,21 @@ static int plan_grid(float L, float ll, Grid3* g) {
     int bits = 1;
     while (bits < 61 && ldexp(1.0, bits) < cells) bits++;
     g->key_bits = bits + 3;
-    double side = (double)L / (2.0 * (double)nc);
+    double side = E / (2.0 * (double)nc);
     g->autolink = 3.0 * side * side * (1.0 + 1e-5) <= (double)ll * (double)ll * (1.0 - 1e-5);
-    g->octfilter = nc >= 3;
+    g->octfilter = !periodic || nc >= 3;
     return RS_OK;
 }
 
-int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
-              int32_t* labels, int64_t* n_groups, hipStream_t st) {
-    Grid3 g;
-    RS_TRY(plan_grid(L, ll, &g));
-    const int BT = 256;
-    // footprint (upper bounds: octants and cells <= n)
-    // dense row table when the grid has few rows for the particle count
+// dense row table when the grid has few rows for the particle count
+static bool use_row_table(int64_t n, const Grid3& g) {
     const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
-    const bool row_table = rows <= std::max<uint64_t>(4 * (uint64_t)n, 1u << 20);
+    return rows <= std::max<uint64_t>(4 * (uint64_t)n, 1u << 20);
+}
+
+// device bytes of one 3D pass (upper bounds: octants and cells <= n)
+size_t fof3d_bytes(int64_t n, const Grid3& g) {
+    const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
     size_t bytes = 0;
     auto add = [&](size_t b) { bytes += arena_round(b); };
     add(8 * n); add(8 * n);                 // keys in / out
@@ -436,11 +467,35 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     add(4 * (n + 1));                       // octant union-find
     const int64_t cap_heavy = n / 4 + 1024;
     add(8 * cap_heavy); add(64);            // deferred octant pairs, count
-    if (row_table) add(4 * (rows + 1));      // row table
+    if (use_row_table(n, g)) add(4 * (rows + 1));   // row table
     add(sort_temp_bytes(n)); add(scan_temp_bytes(n));
     add(64);                                // counters
-    Arena* ar;
-    RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
+    return bytes;
+}
+
+template <bool PER>
+static int link_pass(const LinkArgs& A, unsigned go, hipStream_t st) {
+    if (A.g.autolink) {
+        RS_TRY(fill_i32(A.n_heavy, 0, 1, st));
+        k_link<true, PER><<<go, 256, 0, st>>>(A);
+        k_link_heavy<PER><<<HEAVY_BLOCKS, 64, 0, st>>>(A);
+    } else {
+        k_link<false, PER><<<go, 256, 0, st>>>(A);
+    }
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+// One 3D pass over the work space `ar` (at least fof3d_bytes(n, g), its bump
+// pointer at the start); `hcnt` is host memory for 16 counters.  Range
+// errors are found before any label is written.
+int fof3d_core(const float* x, const float* y, const float* z, int64_t n, const Grid3& g,
+               const Bounds& B, Arena* ar, int32_t* hcnt, bool instrument, int32_t* labels,
+               int64_t* n_groups, hipStream_t st) {
+    const int BT = 256;
+    const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
+    const bool row_table = use_row_table(n, g);
+    const int64_t cap_heavy = n / 4 + 1024;
     uint64_t* kin = take<uint64_t>(ar, n);
     uint64_t* kout = take<uint64_t>(ar, n);
     int32_t* vin = take<int32_t>(ar, n);
@@ -469,8 +524,8 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     if (!cnt) return RS_EINTERNAL;
 
     unsigned gb = grid_for(n, BT, 1ll << 31);
-    RS_HIP(hipMemsetAsync(cnt, 0, 16 * sizeof(int32_t), st));
-    k_keys<<<gb, BT, 0, st>>>(x, y, z, n, g, kin, vin, cnt + 0);
+    RS_TRY(fill_i32(cnt, 0, 16, st));
+    k_keys<<<gb, BT, 0, st>>>(x, y, z, n, g, B, kin, vin, cnt + 0);
     RS_HIP(hipGetLastError());
     RS_TRY(sort_pairs_u64_i32(kin, kout, vin, perm, n, g.key_bits, stemp, stb, st));
     k_gather3<<<gb, BT, 0, st>>>(perm, x, y, z, n, sx, sy, sz);
@@ -478,8 +533,6 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     RS_HIP(hipGetLastError());
     RS_TRY(scan_exclusive_i32(oflag, oex, n, ctemp, cnt + 1, st));
     RS_TRY(scan_exclusive_i32(cflag, cex, n, ctemp, cnt + 2, st));
-    int32_t* hcnt = nullptr;
-    RS_TRY(host_scratch((void**)&hcnt, 64));
     RS_HIP(hipMemcpyAsync(hcnt, cnt, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
     if (hcnt[0]) return RS_ERANGE;
@@ -510,16 +563,9 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     }
     LinkArgs A{oct_start, oct_bits, cell_oct, cell_key, row_start, n_cell, kout, sx, sy, sz,
                g.autolink ? poct : parent, n_oct, g, heavy, n_heavy, (int32_t)qcap};
-    prof_begin("fof3d_link", st);
-    if (g.autolink) {
-        RS_TRY(fill_i32(n_heavy, 0, 1, st));
-        k_link<true><<<go, 256, 0, st>>>(A);
-        k_link_heavy<<<HEAVY_BLOCKS, 64, 0, st>>>(A);
-    } else {
-        k_link<false><<<go, 256, 0, st>>>(A);
-    }
-    RS_HIP(hipGetLastError());
-    prof_end("fof3d_link", st, (double)n);
+    if (instrument) prof_begin("fof3d_link", st);
+    RS_TRY(B.periodic ? link_pass<true>(A, go, st) : link_pass<false>(A, go, st));
+    if (instrument) prof_end("fof3d_link", st, (double)n);
 
     if (g.autolink) {
         k_flatten<<<go, 256, 0, st>>>(n_oct, poct);
@@ -537,6 +583,94 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     RS_HIP(hipMemcpyAsync(hroots, nroots, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
     if (n_groups) *n_groups = (int64_t)*hroots;
+    return RS_OK;
+}
+
+static Bounds periodic_bounds() {
+    Bounds B{};
+    B.periodic = true;
+    return B;
+}
+
+int fof3d_plan_periodic(float L, float ll, Grid3* g) {
+    const double o[3] = {0.0, 0.0, 0.0};
+    return plan_grid((double)L, ll, true, o, L, g);
+}
+
+int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
+              int32_t* labels, int64_t* n_groups, hipStream_t st) {
+    Grid3 g;
+    RS_TRY(fof3d_plan_periodic(L, ll, &g));
+    Arena* ar;
+    RS_TRY(arena_reserve(AR_BASE, fof3d_bytes(n, g), &ar));
+    int32_t* hcnt = nullptr;
+    RS_TRY(host_scratch((void**)&hcnt, 64));
+    return fof3d_core(x, y, z, n, g, periodic_bounds(), ar, hcnt, true, labels, n_groups, st);
+}
+
+// ghost links: (g, label[g]) for the ghosts g >= n_owned whose group holds an
+// owned particle, i.e. whose label (the group's smallest index) is < n_owned
+__global__ void k_ghost_flag(int64_t n, int64_t n_owned, const int32_t* __restrict__ labels,
+                             int32_t* __restrict__ flag) {
+    const int64_t g = n_owned + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g < n) flag[g - n_owned] = labels[g] < n_owned ? 1 : 0;
+}
+
+__global__ void k_ghost_write(int64_t n, int64_t n_owned, const int32_t* __restrict__ labels,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                              int32_t* __restrict__ links) {
+    const int64_t g = n_owned + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n || !flag[g - n_owned]) return;
+    const int64_t q = pos[g - n_owned];
+    links[2 * q] = (int32_t)g;
+    links[2 * q + 1] = labels[g];
+}
+
+int fof3d_subbox_run(const float* x, const float* y, const float* z, int64_t n,
+                     int64_t n_owned, const float* lo, const float* hi, float gw, float ll,
+                     int32_t* labels, int32_t* ghost_links, int64_t* n_links, hipStream_t st) {
+    Bounds B{};
+    B.periodic = false;
+    B.n_owned = n_owned;
+    double o[3], E = 0.0;
+    for (int a = 0; a < 3; a++) {
+        B.lo[a] = lo[a];
+        B.hi[a] = hi[a];
+        B.glo[a] = (double)lo[a] - (double)gw;
+        B.ghi[a] = (double)hi[a] + (double)gw;
+        o[a] = B.glo[a];
+        E = std::max(E, B.ghi[a] - B.glo[a]);
+    }
+    Grid3 g;
+    RS_TRY(plan_grid(E, ll, false, o, 0.0f, &g));
+    const int64_t ng = n - n_owned;
+    size_t bytes = fof3d_bytes(n, g);
+    const bool links = ghost_links != nullptr;
+    if (links) bytes += 2 * arena_round(4 * (size_t)(ng + 1)) + arena_round(scan_temp_bytes(ng));
+    Arena* ar;
+    RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
+    int32_t* hcnt = nullptr;
+    RS_TRY(host_scratch((void**)&hcnt, 64));
+    RS_TRY(fof3d_core(x, y, z, n, g, B, ar, hcnt, true, labels, nullptr, st));
+    if (!links) return RS_OK;
+    if (ng == 0) {
+        *n_links = 0;
+        return RS_OK;
+    }
+    // the 3D pass's work space is done with: its tail holds the link buffers
+    int32_t* flag = take<int32_t>(ar, ng + 1);
+    int32_t* pos = take<int32_t>(ar, ng + 1);
+    void* ctemp = arena_take(ar, scan_temp_bytes(ng));
+    if (!ctemp) return RS_EINTERNAL;
+    const unsigned gg = grid_for(ng, 256, 1ll << 31);
+    k_ghost_flag<<<gg, 256, 0, st>>>(n, n_owned, labels, flag);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(flag, pos, ng, ctemp, pos + ng, st));
+    k_ghost_write<<<gg, 256, 0, st>>>(n, n_owned, labels, flag, pos, ghost_links);
+    RS_HIP(hipGetLastError());
+    RS_HIP(hipMemcpyAsync(hcnt, pos + ng, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    *n_links = hcnt[0];
     return RS_OK;
 }
 

@@ -117,3 +117,22 @@ def test_halo_props_rejects_bad_arguments_before_device_work(n, box, m, nlev):
     if rc == rs.RS_EDEVICE:
         pytest.skip("argument check passed; no device here")
     assert rc == rs.RS_EINVAL
+
+
+def test_fof3d_subbox_rejects_bad_arguments_before_device_work():
+    lib = rs.load()
+    p = ctypes.c_void_p(1)
+    F3 = ctypes.c_float * 3
+    good_lo, good_hi = F3(0, 0, 0), F3(1, 1, 1)
+    cnt = ctypes.c_int64(5)
+    cases = [(10, 11, good_lo, good_hi, 0.1, 0.2, p, ctypes.byref(cnt)),     # n_owned > n
+             (10, 5, good_lo, F3(1, 0, 1), 0.1, 0.2, p, ctypes.byref(cnt)),  # hi <= lo
+             (10, 5, good_lo, good_hi, -0.1, 0.2, p, ctypes.byref(cnt)),     # ghost width
+             (10, 5, good_lo, good_hi, 0.1, 0.0, p, ctypes.byref(cnt)),      # link length
+             (10, 5, good_lo, good_hi, 0.1, float("nan"), p, ctypes.byref(cnt)),
+             (10, 5, None, good_hi, 0.1, 0.2, p, ctypes.byref(cnt)),
+             (10, 5, good_lo, good_hi, 0.1, 0.2, p, None)]                   # links, no count
+    for n, no, lo, hi, gw, ll, links, nl in cases:
+        rc = lib.rs_fof3d_subbox(p, p, p, n, no, lo, hi, gw, ll, p, links, nl, None)
+        assert rc == rs.RS_EINVAL
+    assert cnt.value == 5

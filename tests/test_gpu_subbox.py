@@ -1,0 +1,108 @@
+"""GPU parity of rs_fof3d_subbox (3D FoF over a non-periodic sub-box with a
+ghost shell) against the CPU oracle: labels and ghost links bit-identical,
+and the decomposition of a periodic box into sub-boxes, unioned on the host,
+equal to the periodic rs_fof3d of the whole box.
+"""
+import numpy as np
+import pytest
+import torch
+
+import decomp
+import oracle
+import paper_2412_18629_amd as rs
+from paper_2412_18629_amd import synth
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+
+
+def _gpu(pos, n_owned, lo, hi, gw, ll):
+    t = [torch.from_numpy(np.ascontiguousarray(pos[:, k], dtype=F32)).cuda() for k in range(3)]
+    lab, links = rs.rs_fof3d_subbox(*t, n_owned, lo, hi, gw, ll)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), links.cpu().numpy()
+
+
+def _check(pos, n_owned, lo, hi, gw, ll):
+    got, gl = _gpu(pos, n_owned, lo, hi, gw, ll)
+    ref, rl = oracle.fof3d_subbox(pos[:, 0], pos[:, 1], pos[:, 2], n_owned, lo, hi, gw, ll)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gl, rl)
+    return ref, rl
+
+
+def _shell(rng, lo, hi, gw, m):
+    g = rng.uniform(lo - gw, hi + gw, (6 * m + 64, 3))
+    g = g[~np.all((g >= lo) & (g < hi), axis=1)][:m]
+    return g.astype(F32)
+
+
+@pytest.mark.parametrize("seed,n_own,n_ghost,ll", [(0, 50000, 12000, 0.2), (1, 200003, 30001, 0.15),
+                                                   (2, 7, 3, 0.5), (3, 40000, 0, 0.3)])
+def test_parity_random_and_clustered(seed, n_own, n_ghost, ll):
+    rng = np.random.default_rng(seed)
+    lo = np.array([10.0, 20.0, 5.0], F32)
+    hi = np.array([18.0, 26.0, 13.5], F32)
+    gw = F32(1.5 * ll)
+    cen = rng.uniform(lo, hi, (40, 3))
+    own = np.concatenate([cen[rng.integers(0, 40, n_own // 2)] +
+                          rng.normal(0, 0.15, (n_own // 2, 3)),
+                          rng.uniform(lo, hi, (n_own - n_own // 2, 3))])
+    own = np.clip(own, lo, np.nextafter(hi, F32(0))).astype(F32)
+    pos = np.concatenate([own, _shell(rng, lo, hi, gw, n_ghost)]) if n_ghost else own
+    ref, links = _check(pos, n_own, lo, hi, gw, F32(ll))
+    if n_ghost and n_own > 1000:
+        assert links.shape[0] > 0
+
+
+def test_dense_clumps_and_faces():
+    # clumps on the sub-box faces and corners (octant auto-link and the
+    # deferred heavy pairs), ghosts packed against the faces
+    rng = np.random.default_rng(7)
+    lo = np.zeros(3, F32)
+    hi = np.full(3, 8.0, F32)
+    gw = F32(0.3)
+    corners = np.array([[0, 0, 0], [8, 8, 8], [0, 8, 4], [4, 0, 8], [4, 4, 4]], np.float64)
+    pts = corners[rng.integers(0, 5, 80000)] + rng.normal(0, 0.08, (80000, 3))
+    inside = np.all((pts >= lo) & (pts < hi), axis=1)
+    own = pts[inside].astype(F32)
+    own = own[np.all((own >= lo) & (own < hi), axis=1)]
+    gh = pts[~inside]
+    gh = gh[np.all((gh >= lo - gw) & (gh < hi + gw), axis=1)].astype(F32)
+    gh = gh[~np.all((gh >= lo) & (gh < hi), axis=1)]
+    _check(np.concatenate([own, gh]), own.shape[0], lo, hi, gw, F32(0.2))
+
+
+@pytest.mark.parametrize("parts", [(2, 1, 1), (2, 2, 2), (3, 1, 2)])
+def test_decomposition_equals_periodic_box(parts):
+    cfg = synth.scaled(synth.CONFIGS["c32"], 200000)
+    arrs = synth.generate(cfg, 1)
+    L = F32(cfg.box)
+    pos = decomp.snap(np.stack([a.numpy() for a in arrs[:3]], 1), float(L))
+    ll = F32(cfg.link_len)
+    t = [torch.from_numpy(np.ascontiguousarray(pos[:, k])).cuda() for k in range(3)]
+    whole, _ = rs.rs_fof3d(*t, L, ll)
+    whole = whole.cpu().numpy()
+    assert np.array_equal(whole, oracle.fof3d(pos[:, 0], pos[:, 1], pos[:, 2], L, ll))
+    res = []
+    for lo, hi in decomp.split(float(L), parts):
+        lp, gid, no = decomp.subbox_inputs(pos, L, lo, hi, 1.5 * float(ll))
+        lab, links = _check(lp, no, lo, hi, 1.5 * float(ll), ll)
+        res.append((gid, no, lab, links))
+    assert np.array_equal(decomp.union_subboxes(pos.shape[0], res), whole)
+
+
+def test_errors_leave_outputs_untouched():
+    lo, hi = [0.0, 0.0, 0.0], [4.0, 4.0, 4.0]
+    pos = torch.tensor([[1.0, 1.0, 1.0], [4.2, 1.0, 1.0]], device="cuda")
+    t = [pos[:, k].contiguous() for k in range(3)]
+    lab = torch.full((2,), -7, dtype=torch.int32, device="cuda")
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_fof3d_subbox(*t, 2, lo, hi, 0.5, 0.2, labels=lab)
+    assert e.value.status == rs.RS_ERANGE
+    assert lab.cpu().tolist() == [-7, -7]
+    with pytest.raises(rs.RsError) as e:
+        rs.rs_fof3d_subbox(*t, 3, lo, hi, 0.5, 0.2, labels=lab)
+    assert e.value.status == rs.RS_EINVAL
+    lab2, links = rs.rs_fof3d_subbox(*t, 1, lo, hi, 0.5, 0.2)
+    assert lab2.cpu().tolist() == [0, 1] and links.shape == (0, 2)
