@@ -84,6 +84,24 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n,
              void* stream);
 
 /*
+ * rs_fof3d_noalloc -- rs_fof3d for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, checks, results and synchronisation
+ * as rs_fof3d, but the pass's work space is a fixed 128 MiB device array
+ * (RS_NOALLOC_SCRATCH_BYTES) that each GPU the library runs on holds from the
+ * library's load until the process ends; the call allocates nothing.  A pass
+ * needs about 110 bytes per particle (its sort, tables, union-find and the
+ * grid's row table): about 1.1 million particles fit, and a call that needs
+ * more returns RS_EINVAL before any device work.  Every call on one GPU
+ * shares that GPU's array (whatever an earlier call left there is cleared or
+ * overwritten before use), so calls that overlap on one GPU, from several
+ * host threads or on several streams, race and are not supported.
+ */
+#define RS_NOALLOC_SCRATCH_BYTES (128u << 20)
+int rs_fof3d_noalloc(const float* x, const float* y, const float* z, int64_t n, float box,
+                     float link_len, int32_t* labels, int64_t* n_groups, void* stream);
+
+/*
  * rs_fof3d_subbox -- 3D friends-of-friends over one process's non-periodic
  * sub-box with a ghost shell (the paper's decomposition, Parallelization
  * section: each process runs the 3D FoF over its own sub-box, and halos are

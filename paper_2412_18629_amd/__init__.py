@@ -60,6 +60,8 @@ def load():
                                   ctypes.c_float, ctypes.c_double, ctypes.c_uint32)
     lib.rs_fof3d.argtypes = [P, P, P, i64, f32, f32, P, ctypes.POINTER(i64), P]
     lib.rs_fof3d.restype = ctypes.c_int
+    lib.rs_fof3d_noalloc.argtypes = [P, P, P, i64, f32, f32, P, ctypes.POINTER(i64), P]
+    lib.rs_fof3d_noalloc.restype = ctypes.c_int
     lib.rs_fof3d_subbox.argtypes = [P, P, P, i64, i64, P, P, f32, f32, P, P,
                                     ctypes.POINTER(i64), P]
     lib.rs_fof3d_subbox.restype = ctypes.c_int

@@ -8,6 +8,8 @@
 namespace rs {
 int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
               int32_t* labels, int64_t* n_groups, hipStream_t st);
+int fof3d_noalloc_run(const float* x, const float* y, const float* z, int64_t n, float L,
+                      float ll, int32_t* labels, int64_t* n_groups, hipStream_t st);
 int fof3d_subbox_run(const float* x, const float* y, const float* z, int64_t n,
                      int64_t n_owned, const float* lo, const float* hi, float gw, float ll,
                      int32_t* labels, int32_t* ghost_links, int64_t* n_links, hipStream_t st);
@@ -48,6 +50,21 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float bo
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
                          static_cast<hipStream_t>(stream));
+}
+
+int rs_fof3d_noalloc(const float* x, const float* y, const float* z, int64_t n, float box,
+                     float link_len, int32_t* labels, int64_t* n_groups, void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31) return RS_EINVAL;
+    if (!(box > 0.0f) || !isfinite(box)) return RS_EINVAL;
+    if (!(link_len > 0.0f) || !(link_len < 0.5f * box)) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !labels)) return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    if (n == 0) {
+        if (n_groups) *n_groups = 0;
+        return RS_OK;
+    }
+    return rs::fof3d_noalloc_run(x, y, z, n, box, link_len, labels, n_groups,
+                                 static_cast<hipStream_t>(stream));
 }
 
 int rs_fof3d_subbox(const float* x, const float* y, const float* z, int64_t n, int64_t n_owned,

@@ -608,6 +608,42 @@ int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L
     return fof3d_core(x, y, z, n, g, periodic_bounds(), ar, hcnt, true, labels, n_groups, st);
 }
 
+// ---------------------------------------------------------------------------
+// the 3D pass without allocation: its work space is a fixed device array
+// ---------------------------------------------------------------------------
+
+// 128 MiB per device, held from the library's load until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device
+// memory: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+static void* g_scratch_ptr[64];
+static int32_t g_noalloc_counts[64][16];   // host counters read back by the pass
+
+int fof3d_noalloc_run(const float* x, const float* y, const float* z, int64_t n, float L,
+                      float ll, int32_t* labels, int64_t* n_groups, hipStream_t st) {
+    Grid3 g;
+    RS_TRY(fof3d_plan_periodic(L, ll, &g));
+    if (fof3d_bytes(n, g) > NOALLOC_SCRATCH_BYTES) return RS_EINVAL;
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return RS_EDEVICE;
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return RS_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    Arena a;
+    a.base = static_cast<char*>(g_scratch_ptr[dev]);
+    a.cap = NOALLOC_SCRATCH_BYTES;
+    a.off = 0;
+    return fof3d_core(x, y, z, n, g, periodic_bounds(), &a, g_noalloc_counts[dev], false, labels,
+                      n_groups, st);
+}
+
 // ghost links: (g, label[g]) for the ghosts g >= n_owned whose group holds an
 // owned particle, i.e. whose label (the group's smallest index) is < n_owned
 __global__ void k_ghost_flag(int64_t n, int64_t n_owned, const int32_t* __restrict__ labels,
