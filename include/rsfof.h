@@ -62,6 +62,9 @@ enum {
 #define RS_NFEAT 24
 /* MLP parameters: W1[64][24], b1[64], W2[64][64], b2[64], W3[64], b3 */
 #define RS_MLP_NPARAM 5825
+/* Size of the proposer blob rs_phase_fof_batch takes: "RSM1" + float32
+ * mean[RS_NFEAT], std[RS_NFEAT], params[RS_MLP_NPARAM]. */
+#define RS_MODEL_BYTES (4 + 4 * (2 * RS_NFEAT + RS_MLP_NPARAM))
 
 /*
  * rs_fof3d -- 3D friends-of-friends over one periodic box (the per-process
@@ -187,8 +190,9 @@ typedef struct rs_tree {
  *   min_sub     >= 2, smallest child kept (10).
  *   f           0 < f <= 1, linked fraction (0.7).
  *   flags       RS_PLAIN, RS_BATCHED or RS_LEARNED, optionally | RS_FEATURES.
- *   model       (host) proposer blob ("RSM1" + floats, see below) for
- *               RS_LEARNED, else NULL.  RS_LEARNED applies the proposal to
+ *   model       (host) proposer blob of RS_MODEL_BYTES bytes ("RSM1" + floats,
+ *               see below) for RS_LEARNED, else NULL; only the tag is checked,
+ *               so a shorter buffer is read past its end.  RS_LEARNED applies the proposal to
  *               nodes above the workgroup size (2048 members); smaller nodes
  *               are split exactly as in RS_BATCHED.
  *   out         (host) receives a new rs_tree* (release with rs_free).

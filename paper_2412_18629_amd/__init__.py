@@ -20,6 +20,8 @@ RS_PLAIN, RS_BATCHED, RS_LEARNED = 0, 1, 2
 RS_FEATURES = 0x100
 RS_NFEAT = 24
 RS_MLP_NPARAM = 5825
+MODEL_FLOATS = 2 * RS_NFEAT + RS_MLP_NPARAM      # mean[24], std[24], params
+MODEL_BYTES = 4 + 4 * MODEL_FLOATS               # "RSM1" tag + floats
 
 EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_version",
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
@@ -257,6 +259,10 @@ def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_s
     in canonical (level, min_index) order, ``deepest`` per particle, and the
     statistics n_accepted, n_fallback, n_levels."""
     lib = load()
+    if model is not None and not isinstance(model, (bytes, bytearray)):
+        raise TypeError("model must be a bytes blob")
+    if model is not None and (len(model) != MODEL_BYTES or bytes(model[:4]) != b"RSM1"):
+        raise ValueError(f"model must be the {MODEL_BYTES}-byte RSM1 proposer blob")
     n = x.numel()
     arrs = (x, y, z, vx, vy, vz)
     names = ("x", "y", "z", "vx", "vy", "vz")
@@ -265,8 +271,6 @@ def rs_phase_fof_batch(x, y, z, vx, vy, vz, box, fof_labels, min_group=10, min_s
             raise ValueError(f"{nm} size differs from x")
     ptrs = [_dev(t, torch.float32, nm) for t, nm in zip(arrs, names)]
     lab = _dev(fof_labels, torch.int32, "fof_labels")
-    if model is not None and not isinstance(model, (bytes, bytearray)):
-        raise TypeError("model must be a bytes blob")
     mbuf = ctypes.create_string_buffer(bytes(model), len(model)) if model is not None else None
     out = ctypes.POINTER(_Tree)()
     st = _stream(stream)
@@ -352,6 +356,8 @@ def _ck(rc, where):
 
 
 def rs_mlp_forward(params, X, stream=None):
+    if params.numel() != RS_MLP_NPARAM or X.dim() != 2 or X.shape[1] != RS_NFEAT:
+        raise ValueError("params must hold RS_MLP_NPARAM floats and X be (n, RS_NFEAT)")
     y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
     _ck(load().rs_mlp_forward(_dev(params, torch.float32, "params"), _dev(X, torch.float32, "X"),
                               X.shape[0], _dev(y, torch.float32, "y"), _stream(stream)),
@@ -360,6 +366,9 @@ def rs_mlp_forward(params, X, stream=None):
 
 
 def rs_mlp_grad(params, X, t, stream=None):
+    if params.numel() != RS_MLP_NPARAM or X.dim() != 2 or X.shape[1] != RS_NFEAT or \
+            t.numel() != X.shape[0]:
+        raise ValueError("params, X (n, RS_NFEAT) and t (n) have inconsistent sizes")
     g = torch.empty(RS_MLP_NPARAM, dtype=torch.float32, device=X.device)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
     _ck(load().rs_mlp_grad(_dev(params, torch.float32, "params"), _dev(X, torch.float32, "X"),
@@ -369,6 +378,9 @@ def rs_mlp_grad(params, X, t, stream=None):
 
 
 def rs_mlp_train_step(params, m, v, step, X, t, lr, loss, stream=None):
+    if any(a.numel() != RS_MLP_NPARAM for a in (params, m, v)) or X.dim() != 2 or \
+            X.shape[1] != RS_NFEAT or t.numel() != X.shape[0] or loss.numel() < 1:
+        raise ValueError("params, m, v, X (n, RS_NFEAT), t (n) have inconsistent sizes")
     _ck(load().rs_mlp_train_step(_dev(params, torch.float32, "params"),
                                  _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"),
                                  int(step), _dev(X, torch.float32, "X"),
@@ -385,6 +397,10 @@ def rs_mlp_standardize(X, mean, std, compute=True, stream=None):
 
 
 def rs_mlp_infer(model, feats, stream=None):
+    if model.numel() != MODEL_FLOATS:
+        raise ValueError(f"model must hold {MODEL_FLOATS} floats")
+    if feats.dim() != 2 or feats.shape[1] != RS_NFEAT:
+        raise ValueError(f"features must be (n, {RS_NFEAT})")
     out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
     _ck(load().rs_mlp_infer(_dev(model, torch.float32, "model"),
                             feats.shape[0], _dev(feats, torch.float32, "features"),

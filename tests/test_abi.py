@@ -136,3 +136,16 @@ def test_fof3d_subbox_rejects_bad_arguments_before_device_work():
         rc = lib.rs_fof3d_subbox(p, p, p, n, no, lo, hi, gw, ll, p, links, nl, None)
         assert rc == rs.RS_EINVAL
     assert cnt.value == 5
+
+
+def test_binding_checks_the_proposer_blob():
+    # a truncated or foreign blob never reaches the library (it copies a
+    # fixed number of floats from it)
+    from paper_2412_18629_amd import learn
+    blob = learn.load_model()
+    assert len(blob) == rs.MODEL_BYTES
+    t = torch.zeros(4)
+    for bad in (blob[:-4], b"XXXX" + blob[4:], blob + b"\0\0\0\0"):
+        with pytest.raises(ValueError):
+            rs.rs_phase_fof_batch(t, t, t, t, t, t, 1.0, torch.zeros(4, dtype=torch.int32),
+                                  flags=rs.RS_LEARNED, model=bad)
