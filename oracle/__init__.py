@@ -52,6 +52,7 @@ def _load():
     lib.oracle_node_nn.argtypes = [P, P, P, P, P, P, f32, P, i64, f32, f32, P]
     lib.oracle_node_norm.argtypes = [P, P, P, P, P, P, f32, P, i64, P]
     lib.oracle_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P]
+    lib.oracle_seed_assign.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P, P, P]
     lib.oracle_fof3d_subbox.argtypes = [P, P, P, i64, i64, P, P, f32, f32, ctypes.c_int, P]
     _lib = lib
     return lib
@@ -190,4 +191,24 @@ def halo_props(x, y, z, vx, vy, vz, box, parent, min_index, deepest):
                                _ptr(mi), _ptr(dp), _ptr(out))
     if rc != 0:
         raise OracleError(f"oracle_halo_props failed: {rc}")
+    return out
+
+
+def seed_assign(x, y, z, vx, vy, vz, box, parent, deepest, a, c, props):
+    """Seed (leaf node) each particle is assigned to, int32[n] (-1 outside
+    every node); props as halo_props returns it."""
+    lib = _load()
+    arrs = [_f32(q) for q in (x, y, z, vx, vy, vz)]
+    par = np.ascontiguousarray(np.asarray(parent, dtype=np.int32))
+    dp = np.ascontiguousarray(np.asarray(deepest, dtype=np.int32))
+    fa, fc = _f32(a), _f32(c)
+    pr = np.ascontiguousarray(np.asarray(props, dtype=np.float32))
+    m = par.size
+    if pr.shape != (len(PROP_NAMES), m):
+        raise ValueError("props has the wrong shape")
+    out = np.empty(arrs[0].size, np.int32)
+    rc = lib.oracle_seed_assign(*[_ptr(q) for q in arrs], arrs[0].size, float(box), m,
+                                _ptr(par), _ptr(dp), _ptr(fa), _ptr(fc), _ptr(pr), _ptr(out))
+    if rc != 0:
+        raise OracleError(f"oracle_seed_assign failed: {rc}")
     return out

@@ -985,3 +985,89 @@ int oracle_halo_props(const float *x, const float *y, const float *z,
     free(cnt); free(start); free(fill); free(mem);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* seed-halo assignment                                                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Completes the hierarchy into a particle-to-halo assignment (the rest of
+ * the subhalo finding the paper's Parallelization section attributes to the
+ * 6D phase-space step; the reading is stated in full in the design notes).
+ * Seeds are the leaves of the hierarchy (nodes without children).  A
+ * particle whose deepest node is a seed belongs to it; a particle whose
+ * deepest node d has children goes to the seed s, among the seeds in d's
+ * subtree, with the smallest
+ *   d^2 = fl(fl(a_s * Dx) + fl(c_s * Dv)),
+ * Dx the fp32 sum ((dx^2 + dy^2) + dz^2) of the nearest-image differences
+ * x_p - centre_s (one periodic shift per axis), Dv the same sum over
+ * v_p - velocity_s without a shift, a_s and c_s the seed's metric factors;
+ * ties go to the smaller node index.  Particles outside every node get -1.
+ * props holds the node properties (oracle_halo_props layout: centre in rows
+ * 0..2, bulk velocity in rows 3..5).  Returns 0, -1 (inconsistent input) or
+ * -3 (memory).
+ */
+int oracle_seed_assign(const float *x, const float *y, const float *z,
+                       const float *vx, const float *vy, const float *vz, int64_t n, float L,
+                       int64_t n_nodes, const int32_t *parent, const int32_t *deepest,
+                       const float *fa, const float *fc, const float *props, int32_t *halo)
+{
+    if (n < 0 || n_nodes < 0 || !(L > 0.0f)) return -1;
+    float h = 0.5f * L;
+    int64_t *nkid = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    if (!nkid) return -3;
+    for (int64_t k = 0; k < n_nodes; k++) {
+        if (parent[k] < -1 || parent[k] >= n_nodes) { free(nkid); return -1; }
+        if (parent[k] >= 0) nkid[parent[k]]++;
+    }
+    /* the seeds of each node's subtree: every leaf is listed under itself and
+       each of its ancestors */
+    int64_t *cnt = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    int64_t *start = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)(n_nodes + 1), sizeof(int64_t));
+    if (!cnt || !start || !fill) { free(nkid); free(cnt); free(start); free(fill); return -3; }
+    for (int64_t s = 0; s < n_nodes; s++) {
+        if (nkid[s]) continue;
+        int64_t depth = 0;
+        for (int64_t k = s; k >= 0; k = parent[k]) {
+            cnt[k]++;
+            if (++depth > n_nodes) { free(nkid); free(cnt); free(start); free(fill); return -1; }
+        }
+    }
+    for (int64_t k = 0; k < n_nodes; k++) start[k + 1] = start[k] + cnt[k];
+    int64_t *seeds = (int64_t *)malloc(sizeof(int64_t) * (size_t)(start[n_nodes] > 0 ? start[n_nodes] : 1));
+    if (!seeds) { free(nkid); free(cnt); free(start); free(fill); return -3; }
+    for (int64_t s = 0; s < n_nodes; s++) {
+        if (nkid[s]) continue;
+        for (int64_t k = s; k >= 0; k = parent[k]) seeds[start[k] + fill[k]++] = s;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int64_t d = deepest[i];
+        if (d < -1 || d >= n_nodes) { halo[i] = -1; continue; }
+        if (d < 0) { halo[i] = -1; continue; }
+        if (!nkid[d]) { halo[i] = (int32_t)d; continue; }
+        float best = INFINITY;
+        int64_t bs = -1;
+        for (int64_t t = start[d]; t < start[d + 1]; t++) {
+            int64_t s = seeds[t];
+            float dx = min_image(x[i] - props[0 * n_nodes + s], L, h);
+            float dy = min_image(y[i] - props[1 * n_nodes + s], L, h);
+            float dz = min_image(z[i] - props[2 * n_nodes + s], L, h);
+            float sx = dx * dx, sy = dy * dy, sz = dz * dz;
+            float t1 = sx + sy;
+            float Dx = t1 + sz;
+            float du = vx[i] - props[3 * n_nodes + s];
+            float dv = vy[i] - props[4 * n_nodes + s];
+            float dw = vz[i] - props[5 * n_nodes + s];
+            float su = du * du, sv = dv * dv, sw = dw * dw;
+            float t2 = su + sv;
+            float Dv = t2 + sw;
+            float u = fa[s] * Dx, w = fc[s] * Dv;
+            float d2 = u + w;
+            if (d2 < best || (d2 == best && s < bs)) { best = d2; bs = s; }
+        }
+        halo[i] = (int32_t)bs;
+    }
+    free(nkid); free(cnt); free(start); free(fill); free(seeds);
+    return 0;
+}

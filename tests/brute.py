@@ -204,3 +204,42 @@ def exact_props(pos, vel, L, ref=0):
                 for i in range(n))
         j.append(s / n / 2 ** 30)
     return cen + vbar + M + j
+
+
+def seed_assign(pos, vel, L, parent, deepest, a, c, props):
+    """Seed of each particle by brute force: the leaf, among the leaves below
+    the particle's deepest node, with the smallest fp32 phase-space distance
+    to the leaf's centre and bulk velocity (ties: smaller node index)."""
+    parent = np.asarray(parent)
+    m = parent.size
+    kids = np.zeros(m, np.int64)
+    np.add.at(kids, parent[parent >= 0], 1)
+    leaves = np.nonzero(kids == 0)[0]
+    below = {k: [] for k in range(m)}
+    for s in leaves:
+        k = s
+        while k >= 0:
+            below[k].append(s)
+            k = parent[k]
+    L32 = F32(L)
+    h = F32(0.5) * L32
+    out = np.full(pos.shape[0], -1, np.int64)
+    for i in range(pos.shape[0]):
+        d = int(deepest[i])
+        if d < 0:
+            continue
+        if kids[d] == 0:
+            out[i] = d
+            continue
+        s = np.array(sorted(below[d]))
+        dxs = []
+        for ax in range(3):
+            t = (pos[i, ax] - props[ax, s]).astype(F32)
+            t = np.where(t > h, t - L32, np.where(t < -h, t + L32, t)).astype(F32)
+            dxs.append(t)
+        Dx = ((dxs[0] * dxs[0]) + (dxs[1] * dxs[1])) + (dxs[2] * dxs[2])
+        dvs = [(vel[i, ax] - props[3 + ax, s]).astype(F32) for ax in range(3)]
+        Dv = ((dvs[0] * dvs[0]) + (dvs[1] * dvs[1])) + (dvs[2] * dvs[2])
+        d2 = (np.asarray(a, F32)[s] * Dx) + (np.asarray(c, F32)[s] * Dv)
+        out[i] = s[np.lexsort((s, d2))[0]]
+    return out.astype(np.int32)
