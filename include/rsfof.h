@@ -252,6 +252,33 @@ int rs_halo_props(const float* x, const float* y, const float* z, const float* v
                   float* props, void* stream);
 
 /*
+ * rs_seed_assign -- assigns every particle of a hierarchy to a seed halo,
+ * completing the subhalo finding of the 6D phase-space step (paper,
+ * Parallelization section; the method is deferred there to the cited
+ * Rockstar paper, so this follows a stated reading):
+ *   seeds are the leaves of the hierarchy (nodes without children); a
+ *   particle whose deepest node is a seed belongs to it; a particle whose
+ *   deepest node d has children goes to the seed s below d with the smallest
+ *   d^2 = fl(fl(a_s * Dx) + fl(c_s * Dv)), Dx the fp32 sum ((dx^2 + dy^2) +
+ *   dz^2) of the nearest-image differences x - centre_s, Dv the same sum of
+ *   v - velocity_s without a shift; ties go to the smaller node index.
+ *   x..vz       [n] fp32 positions (0 <= x < box) and velocities.
+ *   n_nodes ... deepest, a, c: the hierarchy exactly as rs_tree holds it.
+ *   props       [RS_NPROP * n_nodes] as rs_halo_props returns it (centre and
+ *               bulk velocity are read).
+ *   halo        [n] int32 output: the seed's node index, -1 outside every node.
+ * The hierarchy is checked as in rs_halo_props (RS_EINVAL before any output
+ * is written); uses the library's workspace and returns after synchronising
+ * `stream`.  RS_OK, RS_EINVAL, RS_ERANGE, RS_ENOMEM, RS_EDEVICE.
+ */
+int rs_seed_assign(const float* x, const float* y, const float* z, const float* vx,
+                   const float* vy, const float* vz, int64_t n, float box, int64_t n_nodes,
+                   int64_t n_levels, const int32_t* level, const int32_t* parent,
+                   const int32_t* min_index, const int32_t* size, const int32_t* deepest,
+                   const float* a, const float* c, const float* props, int32_t* halo,
+                   void* stream);
+
+/*
  * Linking-length proposer: a small network that predicts ln l of a node from
  * 24 summary features.  It never decides a result: RS_LEARNED verifies every
  * proposal exactly and completes rejected ones with the exact search.  All
@@ -282,7 +309,7 @@ int rs_mlp_infer(const float* model, int64_t n, const float* features, float* ou
  * Instrumentation (not part of the method).  While enabled, the library
  * records HIP events on the launching stream around its main kernels
  * ("fof3d_link", "phase_small", "phase_large_nn", "phase_large_link",
- * "phase_large_nn_fallback", "halo_props") and
+ * "phase_large_nn_fallback", "halo_props", "seed_assign") and
  * accumulates their elapsed time, launch count and processed work units
  * (particles or node members).  rs_profile_enable(0) clears the records.
  * rs_profile_get synchronises on the recorded events; unknown names report

@@ -27,7 +27,7 @@ EXPORTED = ("rs_fof3d", "rs_phase_fof_batch", "rs_free", "rs_strerror", "rs_vers
             "rs_profile_enable", "rs_profile_get", "rs_mlp_forward", "rs_mlp_grad",
             "rs_mlp_train_step", "rs_mlp_standardize", "rs_mlp_infer",
             "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_tune_set", "rs_tune_get",
-            "rs_tune_name", "rs_halo_props", "rs_fof3d_subbox")
+            "rs_tune_name", "rs_halo_props", "rs_fof3d_subbox", "rs_seed_assign")
 
 
 class RsError(RuntimeError):
@@ -88,6 +88,8 @@ def load():
     lib.rs_mlp_infer.argtypes = [P, i64, P, P, P]
     lib.rs_sort_pairs_u64_i32.argtypes = [P, P, P, P, i64, ctypes.c_int, P]
     lib.rs_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, i64, P, P, P, P, P, P, P]
+    lib.rs_seed_assign.argtypes = [P, P, P, P, P, P, i64, f32, i64, i64, P, P, P, P, P, P, P, P,
+                                   P, P]
     lib.rs_release_workspace.argtypes = []
     lib.rs_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int]
     lib.rs_tune_set.restype = ctypes.c_int
@@ -97,7 +99,8 @@ def load():
     lib.rs_tune_name.argtypes = [ctypes.c_int]
     lib.rs_tune_name.restype = ctypes.c_char_p
     for fn in ("rs_mlp_forward", "rs_mlp_grad", "rs_mlp_train_step", "rs_mlp_standardize",
-               "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_halo_props"):
+               "rs_mlp_infer", "rs_sort_pairs_u64_i32", "rs_release_workspace", "rs_halo_props",
+               "rs_seed_assign"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -329,6 +332,39 @@ def rs_halo_props(x, y, z, vx, vy, vz, box, tree, out=None, stream=None):
                                                   "deepest")]
     _ck(lib.rs_halo_props(*ptrs, n, float(box), m, int(tree["n_levels"]), *tp,
                           _dev(out, torch.float32, "out"), _stream(stream)), "rs_halo_props")
+    return out
+
+
+def rs_seed_assign(x, y, z, vx, vy, vz, box, tree, props, out=None, stream=None):
+    """Seed halo (leaf node index, -1 outside every node) of each particle,
+    int32 device tensor [n]; tree as rs_phase_fof_batch returns it, props as
+    rs_halo_props returns it."""
+    lib = load()
+    n = x.numel()
+    arrs = (x, y, z, vx, vy, vz)
+    names = ("x", "y", "z", "vx", "vy", "vz")
+    for t, nm in zip(arrs, names):
+        if t.numel() != n:
+            raise ValueError(f"{nm} size differs from x")
+    m = tree["level"].numel()
+    for k in ("parent", "min_index", "size", "a", "c"):
+        if tree[k].numel() != m:
+            raise ValueError(f"tree field {k} has the wrong size")
+    if tree["deepest"].numel() != n:
+        raise ValueError("tree field deepest has the wrong size")
+    if props.shape != (RS_NPROP, m):
+        raise ValueError("props has the wrong shape")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=x.device)
+    if out.numel() != n:
+        raise ValueError("out has the wrong size")
+    ptrs = [_dev(t, torch.float32, nm) for t, nm in zip(arrs, names)]
+    tp = [_dev(tree[k], torch.int32, k) for k in ("level", "parent", "min_index", "size",
+                                                  "deepest")]
+    _ck(lib.rs_seed_assign(*ptrs, n, float(box), m, int(tree["n_levels"]), *tp,
+                           _dev(tree["a"], torch.float32, "a"), _dev(tree["c"], torch.float32, "c"),
+                           _dev(props, torch.float32, "props"), _dev(out, torch.int32, "out"),
+                           _stream(stream)), "rs_seed_assign")
     return out
 
 

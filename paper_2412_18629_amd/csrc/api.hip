@@ -8,6 +8,11 @@
 namespace rs {
 int fof3d_run(const float* x, const float* y, const float* z, int64_t n, float L, float ll,
               int32_t* labels, int64_t* n_groups, hipStream_t st);
+int seeds_run(const float* x, const float* y, const float* z, const float* vx,
+              const float* vy, const float* vz, int64_t n, float L, int64_t m, int64_t nlev,
+              const int32_t* level, const int32_t* parent, const int32_t* min_index,
+              const int32_t* size, const int32_t* deepest, const float* fa, const float* fc,
+              const float* props, int32_t* halo, hipStream_t st);
 int fof3d_noalloc_run(const float* x, const float* y, const float* z, int64_t n, float L,
                       float ll, int32_t* labels, int64_t* n_groups, hipStream_t st);
 int fof3d_subbox_run(const float* x, const float* y, const float* z, int64_t n,
@@ -125,6 +130,29 @@ int rs_halo_props(const float* x, const float* y, const float* z, const float* v
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::props_run(x, y, z, vx, vy, vz, n, box, n_nodes, n_levels, level, parent,
                          min_index, size, deepest, props, static_cast<hipStream_t>(stream));
+}
+
+int rs_seed_assign(const float* x, const float* y, const float* z, const float* vx,
+                   const float* vy, const float* vz, int64_t n, float box, int64_t n_nodes,
+                   int64_t n_levels, const int32_t* level, const int32_t* parent,
+                   const int32_t* min_index, const int32_t* size, const int32_t* deepest,
+                   const float* a, const float* c, const float* props, int32_t* halo,
+                   void* stream) {
+    if (n < 0 || n >= (int64_t)1 << 31) return RS_EINVAL;
+    if (n_nodes < 0 || n_nodes >= (int64_t)1 << 31) return RS_EINVAL;
+    if (n_levels < 0 || n_levels > n_nodes) return RS_EINVAL;
+    if (n_nodes > 0 && n_levels < 1) return RS_EINVAL;
+    if (!(box > 0.0f) || !isfinite(box)) return RS_EINVAL;
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !deepest || !halo)) return RS_EINVAL;
+    if (n_nodes > 0 && (!level || !parent || !min_index || !size || !a || !c || !props))
+        return RS_EINVAL;
+    if (n == 0 && n_nodes > 0) return RS_EINVAL;
+    RS_TRY(rs::device_ready());
+    if (n == 0) return RS_OK;
+    RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
+    return rs::seeds_run(x, y, z, vx, vy, vz, n, box, n_nodes, n_levels, level, parent,
+                         min_index, size, deepest, a, c, props, halo,
+                         static_cast<hipStream_t>(stream));
 }
 
 int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int32_t* vals_in,

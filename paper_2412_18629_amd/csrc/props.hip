@@ -109,7 +109,8 @@ __global__ void k_pr_offsets(PrTree T, int32_t l, const int32_t* __restrict__ ls
 // A particle at sorted position s in node d's run goes to slot
 // off[d] + childsum[d] + (s - ownscan[d]), ownscan being the exclusive scan
 // of the own counts.  Each run must start at ownscan[d] and hold exactly
-// own[d] particles, else the hierarchy is inconsistent.
+// own[d] particles, else the hierarchy is inconsistent (with slot_of NULL
+// only that is checked).
 __global__ void k_pr_keys(const float* __restrict__ x, const float* __restrict__ y,
                           const float* __restrict__ z, const float* __restrict__ vx,
                           const float* __restrict__ vy, const float* __restrict__ vz,
@@ -154,7 +155,7 @@ __global__ void k_pr_slots(int64_t n, PrTree T, const uint64_t* __restrict__ ske
         atomicOr(err, 2);
         return;
     }
-    slot_of[perm[s]] = off[d] + childsum[d] + (int32_t)rank;
+    if (slot_of) slot_of[perm[s]] = off[d] + childsum[d] + (int32_t)rank;
 }
 
 __global__ void k_pr_place(const float* __restrict__ x, const float* __restrict__ y,
@@ -498,6 +499,222 @@ int props_run(const float* x, const float* y, const float* z, const float* vx,
                                                                  props);
     RS_HIP(hipGetLastError());
     prof_end("halo_props", st, member_levels);
+    RS_HIP(hipStreamSynchronize(st));
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// seed-halo assignment: seeds are the leaves; a particle whose deepest node
+// has children goes to the nearest seed below it under that seed's own
+// metric (ties to the smaller node index)
+// ---------------------------------------------------------------------------
+
+struct SeedRec {
+    float cx, cy, cz, ux, uy, uz, a, c;   // centre, bulk velocity, metric factors
+};
+
+// bottom-up: leaf counts of the nodes of level l added to their parents
+__global__ void k_sd_leafup(PrTree T, int32_t l, const int32_t* __restrict__ lstart,
+                            int32_t* __restrict__ leafcnt) {
+    const int32_t b = lstart[l], e = lstart[l + 1];
+    for (int32_t r = b + blockIdx.x * blockDim.x + threadIdx.x; r < e;
+         r += gridDim.x * blockDim.x)
+        atomicAdd(leafcnt + T.parent[r], leafcnt[r]);
+}
+
+// top-down: each node's run in the leaf list, carved from its parent's
+__global__ void k_sd_leafdown(PrTree T, int32_t l, const int32_t* __restrict__ lstart,
+                              const int32_t* __restrict__ leafcnt, int32_t* __restrict__ lfirst,
+                              int32_t* __restrict__ lfill) {
+    const int32_t b = lstart[l], e = lstart[l + 1];
+    for (int32_t r = b + blockIdx.x * blockDim.x + threadIdx.x; r < e;
+         r += gridDim.x * blockDim.x) {
+        const int32_t p = T.parent[r];
+        lfirst[r] = lfirst[p] + atomicAdd(lfill + p, leafcnt[r]);
+    }
+}
+
+__global__ void k_sd_init(PrTree T, const int32_t* __restrict__ childsum,
+                          int32_t* __restrict__ leafcnt, int32_t* __restrict__ err) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= T.m) return;
+    if (childsum[r] > T.size[r]) atomicOr(err, 2);
+    leafcnt[r] = childsum[r] == 0 ? 1 : 0;
+}
+
+__global__ void k_sd_level0(PrTree T, const int32_t* __restrict__ leafcnt,
+                            const int32_t* __restrict__ own, const int32_t* __restrict__ childsum,
+                            int32_t* __restrict__ l0cnt, int32_t* __restrict__ nitem) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= T.m) return;
+    l0cnt[r] = T.level[r] == 0 ? leafcnt[r] : 0;
+    nitem[r] = childsum[r] > 0 ? (own[r] + 63) / 64 : 0;
+}
+
+__global__ void k_sd_seeds(PrTree T, const int32_t* __restrict__ childsum,
+                           const int32_t* __restrict__ lfirst, const float* __restrict__ props,
+                           const float* __restrict__ fa, const float* __restrict__ fc,
+                           SeedRec* __restrict__ seeds, int32_t* __restrict__ seednode) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= T.m || childsum[r] != 0) return;
+    const int32_t q = lfirst[r];
+    const int64_t m = T.m;
+    seeds[q] = SeedRec{props[r], props[m + r], props[2 * m + r], props[3 * m + r],
+                       props[4 * m + r], props[5 * m + r], fa[r], fc[r]};
+    seednode[q] = r;
+}
+
+__global__ void k_sd_items(PrTree T, const int32_t* __restrict__ nitem,
+                           const int32_t* __restrict__ ioff, int32_t* __restrict__ items) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= T.m) return;
+    for (int32_t c = 0; c < nitem[r]; c++) items[ioff[r] + c] = r;
+}
+
+// particles outside every node (-1) and particles of a seed (the seed)
+__global__ void k_sd_direct(int64_t n, PrTree T, const int32_t* __restrict__ childsum,
+                            int32_t* __restrict__ halo) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t d = T.deepest[i];
+    if (d < 0 || d >= T.m) halo[i] = -1;
+    else if (childsum[d] == 0) halo[i] = d;
+}
+
+// one wavefront per 64 own particles of a node with children: each lane
+// takes one particle, the seeds below the node are read in turn (one
+// uniform 32-byte record each) and the nearest is kept
+__global__ void __launch_bounds__(64)
+k_sd_assign(const float* __restrict__ x, const float* __restrict__ y,
+            const float* __restrict__ z, const float* __restrict__ vx,
+            const float* __restrict__ vy, const float* __restrict__ vz, int32_t total,
+            const int32_t* __restrict__ items, const int32_t* __restrict__ ioff,
+            const int32_t* __restrict__ own, const int32_t* __restrict__ ownscan,
+            const int32_t* __restrict__ perm, const int32_t* __restrict__ lfirst,
+            const int32_t* __restrict__ leafcnt, const SeedRec* __restrict__ seeds,
+            const int32_t* __restrict__ seednode, float L, float h,
+            int32_t* __restrict__ halo) {
+    const int lane = threadIdx.x;
+    for (int32_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int32_t r = __builtin_amdgcn_readfirstlane(items[it]);
+        const int32_t c = it - ioff[r];
+        const int32_t k = c * 64 + lane;
+        if (k >= own[r]) continue;
+        const int32_t i = perm[ownscan[r] + k];
+        const float px = x[i], py = y[i], pz = z[i], pu = vx[i], pv = vy[i], pw = vz[i];
+        const int32_t q0 = __builtin_amdgcn_readfirstlane(lfirst[r]);
+        const int32_t q1 = q0 + __builtin_amdgcn_readfirstlane(leafcnt[r]);
+        float best = INFINITY;
+        int32_t bnode = 0x7fffffff;
+        for (int32_t q = q0; q < q1; q++) {
+            const SeedRec S = seeds[q];
+            const int32_t node = seednode[q];
+            const float Dx = sum_sq3(min_image(px - S.cx, L, h), min_image(py - S.cy, L, h),
+                                     min_image(pz - S.cz, L, h));
+            const float Dv = sum_sq3(pu - S.ux, pv - S.uy, pw - S.uz);
+            const float d2 = metric(S.a, Dx, S.c, Dv);
+            if (d2 < best || (d2 == best && node < bnode)) {
+                best = d2;
+                bnode = node;
+            }
+        }
+        halo[i] = bnode;
+    }
+}
+
+int seeds_run(const float* x, const float* y, const float* z, const float* vx,
+              const float* vy, const float* vz, int64_t n, float L, int64_t m, int64_t nlev,
+              const int32_t* level, const int32_t* parent, const int32_t* min_index,
+              const int32_t* size, const int32_t* deepest, const float* fa, const float* fc,
+              const float* props, int32_t* halo, hipStream_t st) {
+    const int BT = 256;
+    PrTree T{level, parent, min_index, size, deepest, (int32_t)m, (int32_t)nlev};
+    const int64_t cap_items = m + n / 64 + 1;
+    size_t bytes = 0;
+    auto add = [&](size_t b) { bytes += arena_round(b); };
+    add(8 * (size_t)n); add(8 * (size_t)n);               // sort keys in / out
+    add(4 * (size_t)n); add(4 * (size_t)n);               // index in / sorted
+    for (int k = 0; k < 11; k++) add(4 * ((size_t)m + 1)); // per-node tables
+    add(sizeof(SeedRec) * ((size_t)m + 1));               // seed records
+    add(4 * (size_t)cap_items);                           // item -> node
+    add(4 * ((size_t)nlev + 2));                          // level starts
+    add(scan_temp_bytes(m)); add(sort_temp_bytes(n)); add(256);
+    Arena* ar;
+    RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
+    uint64_t* kin = take<uint64_t>(ar, n);
+    uint64_t* kout = take<uint64_t>(ar, n);
+    int32_t* vin = take<int32_t>(ar, n);
+    int32_t* perm = take<int32_t>(ar, n);
+    int32_t* childsum = take<int32_t>(ar, m + 1);
+    int32_t* own = take<int32_t>(ar, m + 1);
+    int32_t* ownscan = take<int32_t>(ar, m + 1);
+    int32_t* leafcnt = take<int32_t>(ar, m + 1);
+    int32_t* lfirst = take<int32_t>(ar, m + 1);
+    int32_t* lfill = take<int32_t>(ar, m + 1);
+    int32_t* l0cnt = take<int32_t>(ar, m + 1);
+    int32_t* nitem = take<int32_t>(ar, m + 1);
+    int32_t* ioff = take<int32_t>(ar, m + 1);
+    int32_t* seednode = take<int32_t>(ar, m + 1);
+    int32_t* spare = take<int32_t>(ar, m + 1);
+    SeedRec* seeds = take<SeedRec>(ar, m + 1);
+    int32_t* items = take<int32_t>(ar, cap_items);
+    int32_t* lstart = take<int32_t>(ar, nlev + 2);
+    void* ctemp = arena_take(ar, scan_temp_bytes(m));
+    const size_t stb = sort_temp_bytes(n);
+    void* stemp = arena_take(ar, stb);
+    // counters: 0 err, 1 own total, 2 level-0 leaves, 3 items
+    int32_t* ctr = take<int32_t>(ar, 16);
+    if (!ctr) return RS_EINTERNAL;
+    (void)spare;
+    int32_t* hc = nullptr;
+    RS_TRY(host_scratch((void**)&hc, 64));
+
+    RS_TRY(fill_i32(ctr, 0, 16, st));
+    RS_TRY(fill_i32(lstart, (int32_t)m, nlev + 2, st));
+    RS_TRY(fill_i32(childsum, 0, m + 1, st));
+    RS_TRY(fill_i32(lfill, 0, m + 1, st));
+    const unsigned gm = grid_for(m, BT, 1ll << 31);
+    const unsigned gn = grid_for(n, BT, 1ll << 31);
+    k_pr_check<<<gm, BT, 0, st>>>(T, n, lstart, childsum, ctr);
+    k_sd_init<<<gm, BT, 0, st>>>(T, childsum, leafcnt, ctr);
+    k_pr_own<<<gm, BT, 0, st>>>(T, childsum, own);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(own, ownscan, m, ctemp, ctr + 1, st));
+    k_pr_keys<<<gn, BT, 0, st>>>(x, y, z, vx, vy, vz, n, L, T, kin, vin, ctr);
+    RS_HIP(hipGetLastError());
+    RS_HIP(hipMemcpyAsync(hc, ctr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (hc[0] & 1) return RS_ERANGE;
+    if (hc[0]) return RS_EINVAL;
+    int kbits = 1;
+    while (kbits < 32 && ((int64_t)1 << kbits) <= m) kbits++;
+    RS_TRY(sort_pairs_u64_i32(kin, kout, vin, perm, n, kbits, stemp, stb, st));
+    k_pr_slots<<<gn, BT, 0, st>>>(n, T, kout, perm, nullptr, childsum, own, ownscan, nullptr,
+                                  ctr);
+    for (int64_t l = nlev - 1; l >= 1; l--)
+        k_sd_leafup<<<1024, BT, 0, st>>>(T, (int32_t)l, lstart, leafcnt);
+    k_sd_level0<<<gm, BT, 0, st>>>(T, leafcnt, own, childsum, l0cnt, nitem);
+    RS_HIP(hipGetLastError());
+    RS_TRY(scan_exclusive_i32(l0cnt, lfirst, m, ctemp, ctr + 2, st));
+    RS_TRY(scan_exclusive_i32(nitem, ioff, m, ctemp, ctr + 3, st));
+    for (int64_t l = 1; l < nlev; l++)
+        k_sd_leafdown<<<1024, BT, 0, st>>>(T, (int32_t)l, lstart, leafcnt, lfirst, lfill);
+    k_sd_seeds<<<gm, BT, 0, st>>>(T, childsum, lfirst, props, fa, fc, seeds, seednode);
+    k_sd_items<<<gm, BT, 0, st>>>(T, nitem, ioff, items);
+    RS_HIP(hipGetLastError());
+    RS_HIP(hipMemcpyAsync(hc, ctr, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (hc[0]) return RS_EINVAL;
+    const int32_t total = hc[3];
+    if (total > cap_items) return RS_EINTERNAL;
+    prof_begin("seed_assign", st);
+    k_sd_direct<<<gn, BT, 0, st>>>(n, T, childsum, halo);
+    if (total > 0)
+        k_sd_assign<<<(unsigned)std::min<int64_t>(total, 1 << 16), 64, 0, st>>>(
+            x, y, z, vx, vy, vz, total, items, ioff, own, ownscan, perm, lfirst, leafcnt, seeds,
+            seednode, L, 0.5f * L, halo);
+    RS_HIP(hipGetLastError());
+    prof_end("seed_assign", st, (double)n);
     RS_HIP(hipStreamSynchronize(st));
     return RS_OK;
 }
