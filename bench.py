@@ -9,9 +9,10 @@ and the CPU oracle timed on a bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--form learned|batched|plain]
 
 The timed form is the learned one (the committed proposer); the line also
-reports the learned form's speed-up over the batched form on the same data
-and over the plain form (one group per launch sequence) on the 256^3
-workload, where one plain step takes seconds rather than minutes.
+reports the learned form's speed-up over the batched form and over the plain
+form (one group per launch sequence) on the same data, the small-node
+kernels' figures, and the halo-property and seed-assignment calls over the
+last step's hierarchy.
 """
 from __future__ import annotations
 
@@ -41,9 +42,14 @@ KERNEL_BYTES = {
     "fof3d_link": 16.0,        # 12 B sorted position in, 4 B parent out, per particle
     "phase_large_nn": 28.0,    # 24 B position+velocity in, 4 B d^2 out, per member
     "phase_large_link": 32.0,  # 24 B pos+vel + 4 B d^2 in, 4 B parent out, per member
-    "phase_small": 32.0,       # 28 B member record in, 4 B deepest out, per member
     "phase_large_nn_fallback": 28.0,
 }
+# the small-node subtree kernels (side streams): 28 B member record in and
+# 4 B deepest node out per member of a subtree root (deeper levels stay in LDS)
+SMALL_BYTES = 32.0
+SMALL_MAX = 2048
+# halo properties: one 24-byte record read per member of every node
+PROPS_BYTES = 24.0
 FLAGS = {"learned": rs.RS_LEARNED, "batched": rs.RS_BATCHED, "plain": rs.RS_PLAIN}
 
 # device symbol and source files of each instrumented kernel (the PMC summary
@@ -54,6 +60,7 @@ KERNEL_SYMBOL = {
     "phase_large_link": ("void rs::k_tile_link<", ["phase_tile.hip", "phase_common.h", "common.h"]),
     "phase_small": ("void rs::k_small_subtree<",
                     ["phase_small.hip", "phase_common.h", "common.h"]),
+    "halo_props": ("rs::k_pr_large(", ["props.hip", "common.h"]),
 }
 CSRC = os.path.join(HERE, "paper_2412_18629_amd", "csrc")
 PMC_SUMMARY = os.path.join(HERE, "profiles", "pmc_traffic_c512.json")
@@ -97,21 +104,32 @@ def _kernel_values(rows, kernel):
     return out
 
 
-# vector ALU: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies its SIMD
-# for 4 cycles (SQ_ACTIVE_INST_VALU counts in those 4-cycle units);
-# GRBM_GUI_ACTIVE is summed over the 8 XCDs
+# vector ALU: 256 CUs x 4 SIMDs of 16 lanes; a wave64 VALU instruction
+# occupies its SIMD for at least 4 cycles.  SQ_INSTS_VALU counts the VALU
+# instructions the wavefronts issued; GRBM_GUI_ACTIVE is the busy cycles,
+# summed over the 8 XCDs.  The busy fraction is then a lower bound (64-bit
+# and transcendental instructions take longer) that cannot exceed 1.
 N_SIMD = 1024
 N_XCD = 8
+VALU_CYCLES = 4
+
+
+def valu_busy(insts, gui_active):
+    """Fraction of the vector-ALU issue cycles used, from SQ_INSTS_VALU and
+    GRBM_GUI_ACTIVE summed over a kernel's dispatches."""
+    if insts <= 0 or gui_active <= 0:
+        return None
+    return insts * VALU_CYCLES / (gui_active / N_XCD * N_SIMD)
 
 
 def pmc_summary(fetch_csv, write_csv, copy_bytes, command, out_path, valu_csv=None):
     """Per-launch HBM traffic of the instrumented kernels from a FETCH_SIZE run
     and a WRITE_SIZE run of this script (with --probe-copy), each counter
     scaled by what it reads for the plain device copy of known size; with a
-    third run of SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE, the fraction of the
-    vector ALU issue slots each kernel used."""
+    third run of SQ_INSTS_VALU and GRBM_GUI_ACTIVE, the fraction of the
+    vector ALU issue cycles each kernel used."""
     fe, wr = _pmc_rows(fetch_csv, "FETCH_SIZE"), _pmc_rows(write_csv, "WRITE_SIZE")
-    va = _pmc_rows(valu_csv, "SQ_ACTIVE_INST_VALU") if valu_csv else {}
+    va = _pmc_rows(valu_csv, "SQ_INSTS_VALU") if valu_csv else {}
     gr = _pmc_rows(valu_csv, "GRBM_GUI_ACTIVE") if valu_csv else {}
 
     def probe(rows):
@@ -130,10 +148,9 @@ def pmc_summary(fetch_csv, write_csv, copy_bytes, command, out_path, valu_csv=No
         res["kernels"][k] = {"symbol": sym, "launches": len(f), "fetch_kib": f, "write_kib": w,
                              "hbm_bytes_per_launch": float(np.mean(per)),
                              "sources_sha256": source_digest(k)}
-        inst = sum(_kernel_values(va, k))
-        cyc = sum(_kernel_values(gr, k))
-        if inst > 0 and cyc > 0:
-            res["kernels"][k]["valu_busy"] = inst * 4.0 / (cyc / N_XCD * N_SIMD)
+        busy = valu_busy(sum(_kernel_values(va, k)), sum(_kernel_values(gr, k)))
+        if busy is not None:
+            res["kernels"][k]["valu_busy"] = busy
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
     return res
@@ -173,6 +190,10 @@ def one_step(arrs, cfg, form, labels, model):
                                  model=model if form == "learned" else None)
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timed(fn, reps=1):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -183,37 +204,99 @@ def timed(fn, reps=1):
 
 
 def speedups(arrs, cfg, labels, model, ms_learned):
-    """Learned over batched on the same data; learned over plain on 256^3."""
+    """Learned over batched and over plain (one group per launch sequence),
+    each timed once on the same data."""
     ms_b, _ = timed(lambda: one_step(arrs, cfg, "batched", labels, model))
-    c2 = synth.CONFIGS["c256"]
-    a2 = synth.generate(c2, 0, device=arrs[0].device)
-    l2 = torch.empty(c2.n, dtype=torch.int32, device=arrs[0].device)
-    one_step(a2, c2, "learned", l2, model)
-    ms_l2, _ = timed(lambda: one_step(a2, c2, "learned", l2, model), reps=2)
-    ms_p2, _ = timed(lambda: one_step(a2, c2, "plain", l2, model))
+    ms_p, _ = timed(lambda: one_step(arrs, cfg, "plain", labels, model))
     return {"vs_batched": ms_b / ms_learned, "batched_ms_per_step": ms_b,
-            "vs_plain": ms_p2 / ms_l2, "plain_workload": "c256 (256^3, 160 Mpc/h, seed 0)",
-            "plain_ms_per_step": ms_p2, "learned_ms_per_step_c256": ms_l2}
+            "vs_plain": ms_p / ms_learned, "plain_ms_per_step": ms_p,
+            "plain_workload": cfg.name}
 
 
-def cpu_baseline(arrs, cfg, target=1600000):
-    """The oracle (single-threaded C) on a cubic sub-box of the same data,
-    run as a periodic box of its own: 3D FoF then the 6D hierarchy."""
-    import oracle
+def small_node_stats(tree, prof_small, steps):
+    """The small-node subtree kernels: members of the subtree roots they load
+    (nodes of at most SMALL_MAX members whose parent is larger or absent) and
+    member-levels they split, per step, against their event time."""
+    size = tree["size"].long()
+    parent = tree["parent"].long()
+    small = size <= SMALL_MAX
+    psize = torch.where(parent >= 0, size[parent.clamp(min=0)],
+                        torch.full_like(size, SMALL_MAX + 1))
+    roots = small & (psize > SMALL_MAX)
+    loaded = int(size[roots].sum().item())
+    levels = int(size[small].sum().item())
+    ms = sum(v[0] for v in prof_small.values()) / steps
+    launches = sum(v[1] for v in prof_small.values()) / steps
+    gbs = SMALL_BYTES * loaded / (ms / 1000.0) / 1e9 if ms > 0 else 0.0
+    return {"members_loaded": loaded, "member_levels": levels, "ms_per_step": ms,
+            "launches_per_step": launches, "algorithmic_bytes": SMALL_BYTES * loaded,
+            "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "note": "side streams, overlapped with the main-stream levels"}
+
+
+def hierarchy_rows(arrs, cfg, tree, reps=3):
+    """Halo properties and seed assignment over the last step's hierarchy."""
+    props = rs.rs_halo_props(*arrs, cfg.box, tree)
+    halo = rs.rs_seed_assign(*arrs, cfg.box, tree, props)
+    torch.cuda.synchronize()
+    rs.rs_profile_enable(True)
+    ms_p, _ = timed(lambda: rs.rs_halo_props(*arrs, cfg.box, tree, out=props), reps)
+    ms_s, _ = timed(lambda: rs.rs_seed_assign(*arrs, cfg.box, tree, props, out=halo), reps)
+    tot, launches, units = rs.rs_profile_get("halo_props")
+    st, sl, _ = rs.rs_profile_get("seed_assign")
+    rs.rs_profile_enable(False)
+    avg = tot / max(launches, 1)
+    per = PROPS_BYTES * units / max(launches, 1)
+    gbs = per / (avg / 1000.0) / 1e9 if avg > 0 else 0.0
+    traffic = measured_pmc("halo_props", cfg.name, "hbm_bytes_per_launch")
+    return {
+        "halo_props": {"ms_per_call": ms_p, "nodes": int(tree["level"].numel()),
+                       "roofline": {"bound": "hbm", "kernel": "halo_props", "achieved": gbs,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                                    "avg_launch_ms": avg,
+                                    "algorithmic_bytes_per_launch": per,
+                                    "member_levels": units / max(launches, 1)}},
+        "seed_assign": {"ms_per_call": ms_s, "kernel_ms": st / max(sl, 1),
+                        "assigned": int((halo >= 0).sum().item())},
+    }
+
+
+def cpu_baseline(arrs, cfg, target=1100000, workers=None):
+    """The oracle (single-threaded C) on one process's sub-box of the same
+    workload, as the paper decomposes the box: the owned particles of a cube
+    plus a ghost shell of width 1.5 ll, the sub-box 3D FoF, then the 6D
+    hierarchy of its groups.  All-core figure: the same sub-box, its 3D FoF
+    single-threaded and its groups' 6D hierarchies dealt to one process per
+    core (at most 16), largest groups first; throughput counts owned
+    particles."""
+    from oracle import baseline
+    import tempfile
+    host = [a.cpu().numpy() for a in arrs]
     side = cfg.box * (target / cfg.n) ** (1.0 / 3.0)
-    x, y, z = arrs[0], arrs[1], arrs[2]
-    m = (x < side) & (y < side) & (z < side)
-    sub = [a[m].cpu().numpy() for a in arrs]
-    n = sub[0].size
-    t0 = time.perf_counter()
-    lab = oracle.fof3d(sub[0], sub[1], sub[2], side, cfg.link_len)
-    t1 = time.perf_counter()
-    oracle.phase_fof(*sub, side, lab, cfg.min_group, cfg.min_sub, cfg.f)
-    t2 = time.perf_counter()
-    return {"value": n / (t2 - t0), "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{n} particles inside the sub-box [0,{side:.2f})^3 Mpc/h of the same "
-                       f"workload, run as a periodic box of that side; 3D FoF "
-                       f"{t1 - t0:.2f} s + 6D {t2 - t1:.2f} s single-threaded")}
+    gw = 1.5 * cfg.link_len
+    sub, no, lo, hi = baseline.cut(host, (gw, gw, gw), side, gw)
+    del host
+    no, nt, t3, t6, lab = baseline.run_one((sub, no, lo, hi, gw, cfg.box, cfg.link_len,
+                                            cfg.min_group, cfg.min_sub, cfg.f))
+    progress(f"oracle on one sub-box: {t3:.1f} s 3D + {t6:.1f} s 6D")
+    ncpu = os.cpu_count() or 1
+    workers = workers or max(1, min(16, ncpu))
+    parts = baseline.split_groups(sub, lab, cfg.min_group, workers)
+    res, wall = baseline.run_parts(parts, cfg.box, cfg.min_group, cfg.min_sub, cfg.f,
+                                   tempfile.gettempdir(), progress)
+    slowest = max(r[1] for r in res)
+    return {"value": no / (t3 + t6), "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one process's sub-box of the same workload: the cube "
+                       f"[{lo[0]:.3f}, {hi[0]:.3f})^3 Mpc/h, {no} owned particles and "
+                       f"{nt - no} ghosts in a {gw:.4g} Mpc/h shell; sub-box 3D FoF "
+                       f"{t3:.2f} s + 6D hierarchy {t6:.2f} s, single-threaded"),
+            "all_core": {"value": no / (t3 + slowest), "unit": "particles/s",
+                         "cores": workers, "host_cpus": ncpu, "kind": "oracle",
+                         "sample": (f"the same sub-box: 3D FoF {t3:.2f} s single-threaded, "
+                                    f"then its groups' 6D hierarchies in {workers} processes "
+                                    f"at once (slowest {slowest:.2f} s; {wall:.2f} s wall "
+                                    f"with process start-up)")}}
 
 
 def main():
@@ -225,6 +308,8 @@ def main():
     ap.add_argument("--form", default="learned", choices=["learned", "batched", "plain"])
     ap.add_argument("--no-speedup", action="store_true", help="skip the form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the halo-property and seed-assignment timings")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 3 times (a plain "
                          "copy kernel of known size, for calibrating byte counters)")
@@ -234,7 +319,7 @@ def main():
                          "with --probe-copy MIB, then exit")
     ap.add_argument("--pmc-valu", default=None, metavar="VALU_CSV",
                     help="with --pmc-summary: counter_collection.csv of a run with "
-                         "SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE")
+                         "SQ_INSTS_VALU and GRBM_GUI_ACTIVE")
     ap.add_argument("--pmc-command", default="", help="command recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -275,8 +360,8 @@ def main():
     # small subtrees (level 0, and the small children of each large-node level)
     # run on side streams beside the large-node levels; their event spans
     # overlap other work, so they are reported, not ranked
-    overlap = {k: rs.rs_profile_get(k)[0] / args.steps
-               for k in ("phase_small_level0", "phase_small_children")}
+    prof_small = {k: rs.rs_profile_get(k)
+                  for k in ("phase_small_level0", "phase_small_children")}
     rs.rs_profile_enable(False)
 
     ms = (t1 - t0) * 1000.0 / args.steps
@@ -303,8 +388,7 @@ def main():
                    "nodes_per_s": int(tree["level"].numel()) / (ms / 1000.0),
                    "acceptance_rate": (tree["n_accepted"] /
                                        max(1, tree["n_accepted"] + tree["n_fallback"])),
-                   "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
-                   "overlapped_ms_per_step": overlap},
+                   "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
@@ -314,10 +398,17 @@ def main():
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    progress(f"{args.steps} steps at {ms:.1f} ms")
+    line["small_node_kernels"] = small_node_stats(tree, prof_small, args.steps)
+    if not args.no_rows:
+        line["hierarchy_rows"] = hierarchy_rows(arrs, cfg, tree)
+        progress("halo properties and seed assignment timed")
     if args.form == "learned" and not args.no_speedup:
         line["learned_speedup"] = speedups(arrs, cfg, labels, model, ms)
+        progress("batched and plain forms timed")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(arrs, cfg)
+        progress("oracle baseline timed")
     if args.probe_copy > 0:
         src = torch.ones(args.probe_copy * (1 << 18), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

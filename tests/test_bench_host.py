@@ -47,7 +47,7 @@ def test_pmc_summary_calibration_and_occupancy(tmp_path):
     fetch += [_row(10, link, "FETCH_SIZE", 600.0), _row(10, link, "FETCH_SIZE", 400.0),
               _row(11, link, "FETCH_SIZE", 3000.0)]
     write += [_row(10, link, "WRITE_SIZE", 10.0), _row(11, link, "WRITE_SIZE", 30.0)]
-    valu = [_row(10, link, "SQ_ACTIVE_INST_VALU", 5.0e6), _row(11, link, "SQ_ACTIVE_INST_VALU", 3.0e6),
+    valu = [_row(10, link, "SQ_INSTS_VALU", 5.0e6), _row(11, link, "SQ_INSTS_VALU", 3.0e6),
             _row(10, link, "GRBM_GUI_ACTIVE", 8.0e4), _row(11, link, "GRBM_GUI_ACTIVE", 8.0e4)]
     out = tmp_path / "summary.json"
     res = bench.pmc_summary(_write(tmp_path / "f.csv", fetch), _write(tmp_path / "w.csv", write),
@@ -100,3 +100,24 @@ def test_workload_description_names_the_cube():
     assert "(1024^3)" in bench.workload_description(synth.CONFIGS["c1024"])
     odd = synth.scaled(synth.CONFIGS["c32"], 1000001)
     assert "(1000001)" in bench.workload_description(odd)
+
+
+def test_valu_busy_is_a_fraction():
+    # every SIMD issuing a 4-cycle instruction each 4 cycles is the ceiling
+    cycles = 1.0e6
+    full = bench.N_SIMD * cycles / bench.VALU_CYCLES
+    assert bench.valu_busy(full, cycles * bench.N_XCD) == pytest.approx(1.0)
+    assert bench.valu_busy(full / 4, cycles * bench.N_XCD) == pytest.approx(0.25)
+    assert bench.valu_busy(0, 1.0) is None
+
+
+def test_small_node_stats_count_subtree_roots():
+    import torch
+    # node sizes: a large level-0 node (3000) with a small child (500, a
+    # subtree root) that has a child (100, inside the subtree); a small
+    # level-0 node (40, a root)
+    tree = {"size": torch.tensor([3000, 40, 500, 100]), "parent": torch.tensor([-1, -1, 0, 2])}
+    st = bench.small_node_stats(tree, {"a": (10.0, 2, 0.0), "b": (10.0, 1, 0.0)}, steps=2)
+    assert st["members_loaded"] == 540 and st["member_levels"] == 640
+    assert st["ms_per_step"] == 10.0 and st["launches_per_step"] == 1.5
+    assert st["achieved_gbs"] == pytest.approx(32.0 * 540 / 0.01 / 1e9)
