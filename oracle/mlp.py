@@ -64,3 +64,24 @@ def init(seed=0):
         else:
             parts.append(np.zeros(int(np.prod(shape))))
     return np.concatenate(parts)
+
+
+def adam_update(p, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) in fp64: moments
+    m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2, bias-corrected
+    m_hat = m / (1 - b1^t), v_hat = v / (1 - b2^t), then
+    p <- p - lr m_hat / (sqrt(v_hat) + eps).  Returns new (p, m, v)."""
+    p, m, v, g = (np.asarray(a, np.float64) for a in (p, m, v, g))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def adam_step(p, m, v, step, X, t, lr):
+    """One training step: the loss before the update, then Adam on the
+    minibatch gradient.  Returns (p, m, v, loss)."""
+    lo = loss(p, X, t)
+    p, m, v = adam_update(p, m, v, grad(p, X, t), step, lr)
+    return p, m, v, lo

@@ -9,6 +9,7 @@ R is a dict of host arrays:
   cperm, cstart coarse periodic cell lists (cell side >= ll; nc per axis)
   nc, side      cells per axis and cell side
   tree          node fields and deepest
+  props, halo   (optional) rs_halo_props rows [15, nodes] and rs_seed_assign [n]
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -75,7 +76,9 @@ def check_3d(R, cfg, g):
 
 
 def check_subtree(R, cfg, g, root_of, canon_root):
-    """The subtree of group g equals the oracle hierarchy of its member set."""
+    """The subtree of group g equals the oracle hierarchy of its member set;
+    with props and halo in R, its nodes' halo properties and its particles'
+    seeds equal the oracle's, computed from the oracle's hierarchy."""
     mem = members(R, g)
     h = R["host"]
     ref = oracle.phase_fof(*[a[mem] for a in h], cfg.box, np.zeros(mem.size, np.int32),
@@ -97,6 +100,17 @@ def check_subtree(R, cfg, g, root_of, canon_root):
         bad.append(f"group {g}: parent")
     if not np.array_equal(where[T["deepest"][mem]], ref["deepest"]):
         bad.append(f"group {g}: deepest")
+    if bad or "props" not in R:
+        return bad
+    # halo properties and seeds of the subtree, from the oracle's own hierarchy
+    sub_h = [a[mem] for a in h]
+    P = oracle.halo_props(*sub_h, cfg.box, ref["parent"], ref["min_index"], ref["deepest"])
+    if not np.array_equal(R["props"][:, sub].view(np.int32), P.view(np.int32)):
+        bad.append(f"group {g}: halo properties")
+    seeds = oracle.seed_assign(*sub_h, cfg.box, ref["parent"], ref["deepest"], ref["a"],
+                               ref["c"], P)
+    if not np.array_equal(R["halo"][mem], sub[seeds]):
+        bad.append(f"group {g}: seeds")
     return bad
 
 
@@ -122,7 +136,8 @@ def stratified(sizes, groups, n_pick, min_group, seed=0):
 def check_all(R, cfg, n_sample=64, subtree_max=150000, closure_max=None, log=print):
     """Structural invariants of the whole tree, level-0 moments of every
     group, 3D closure of sampled groups (up to closure_max members when
-    given) and 6D subtrees of sampled groups up to subtree_max members.
+    given) and 6D subtrees of sampled groups (up to subtree_max members
+    when given).
     Raises AssertionError on the first failure."""
     T, n = R["tree"], cfg.n
     h = R["host"]
@@ -185,7 +200,8 @@ def check_all(R, cfg, n_sample=64, subtree_max=150000, closure_max=None, log=pri
         r3 = list(ex.map(lambda g: check_3d(R, cfg, g), pick3))
     bad3 = [(g, s, r) for ok, g, s, r in r3 if not ok]
     assert not bad3, bad3
-    deep = [g for g in pick if cnt[g] <= subtree_max]
+    deep = [g for g in pick if subtree_max is None or cnt[g] <= subtree_max]
+    deep.sort(key=lambda g: -cnt[g])          # largest first on the pool
     with ThreadPoolExecutor(WORKERS) as ex:
         r6 = list(ex.map(lambda g: check_subtree(R, cfg, g, root_of, canon_root), deep))
     bad6 = [b for r in r6 for b in r]

@@ -16,8 +16,11 @@ def _oracle_result(cfg, seed):
     ref = oracle.phase_fof(*h, cfg.box, lab, cfg.min_group, cfg.min_sub, cfg.f)
     order = np.argsort(lab, kind="stable")
     cperm, cstart, nc, side = cell_lists_numpy(*h[:3], cfg.box)
+    props = oracle.halo_props(*h, cfg.box, ref["parent"], ref["min_index"], ref["deepest"])
+    halo = oracle.seed_assign(*h, cfg.box, ref["parent"], ref["deepest"], ref["a"], ref["c"],
+                              props)
     return dict(host=h, labels=lab, order=order, sorted_labels=lab[order], cperm=cperm,
-                cstart=cstart, nc=nc, side=side, tree=ref)
+                cstart=cstart, nc=nc, side=side, tree=ref, props=props, halo=halo)
 
 
 @pytest.fixture(scope="module")
@@ -36,10 +39,13 @@ def _copy(R):
     S = dict(R)
     S["tree"] = {k: v.copy() for k, v in R["tree"].items()}
     S["labels"] = R["labels"].copy()
+    S["props"] = R["props"].copy()
+    S["halo"] = R["halo"].copy()
     return S
 
 
-@pytest.mark.parametrize("what", ["l2", "a", "deepest", "parent", "label_split"])
+@pytest.mark.parametrize("what", ["l2", "a", "deepest", "parent", "label_split", "props",
+                                  "seed"])
 def test_checks_catch_planted_errors(small, what):
     cfg, R = small
     S = _copy(R)
@@ -56,6 +62,13 @@ def test_checks_catch_planted_errors(small, what):
         v = int(np.flatnonzero(T["level"] == 1)[0])
         l0 = np.flatnonzero(T["level"] == 0)
         T["parent"][v] = l0[l0 != T["parent"][v]][0]
+    elif what == "props":                # every node's xy tensor element, one ulp off
+        S["props"][9, :] = np.nextafter(S["props"][9, :], np.float32(np.inf))
+    elif what == "seed":                 # particles of a node with children all sent
+        kids = np.zeros(T["level"].size, np.int64)   # to one seed
+        np.add.at(kids, T["parent"][T["parent"] >= 0], 1)
+        own = np.flatnonzero((T["deepest"] >= 0) & (kids[np.maximum(T["deepest"], 0)] > 1))
+        S["halo"][own] = S["halo"][own[0]]
     else:                                # a whole group relabelled as its own split
         big = np.bincount(S["labels"]).argmax()
         mem = np.flatnonzero(S["labels"] == big)
