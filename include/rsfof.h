@@ -18,8 +18,11 @@
  *     leaks.  Out-of-range or non-finite coordinates are detected on the
  *     device before any output is written and reported as RS_ERANGE.
  *   - `stream` is a hipStream_t (NULL = the default stream).  The library
- *     keeps one grow-only workspace per device; calls that overlap on one
- *     device from several host threads are not supported.
+ *     keeps one grow-only workspace per device.  Calls on one device from
+ *     several host threads are serialised by a per-device lock (each holds it
+ *     until it returns); the stream-ordered rs_mlp_train_step and
+ *     rs_sort_pairs_u64_i32 may still have work in flight after returning,
+ *     so they must not overlap other calls on other streams of that device.
  *
  * Pair arithmetic (fixed, identical in every kernel):
  *   dx = fl(xi - xj) followed by one periodic shift (dx > box/2: dx - box;
@@ -88,17 +91,18 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n,
 
 /*
  * rs_fof3d_noalloc -- rs_fof3d for callers that cannot allocate device
- * memory (code under HIP graph capture, tight serving loops, harnesses that
- * forbid hipMalloc).  Same arguments, checks, results and synchronisation
- * as rs_fof3d, but the pass's work space is a fixed 128 MiB device array
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, checks, results and synchronisation as rs_fof3d (it reads
+ * counters back mid-pass, so like rs_fof3d it cannot be recorded into a
+ * graph), but the pass's work space is a fixed 128 MiB device array
  * (RS_NOALLOC_SCRATCH_BYTES) that each GPU the library runs on holds from the
  * library's load until the process ends; the call allocates nothing.  A pass
  * needs about 110 bytes per particle (its sort, tables, union-find and the
  * grid's row table): about 1.1 million particles fit, and a call that needs
  * more returns RS_EINVAL before any device work.  Every call on one GPU
  * shares that GPU's array (whatever an earlier call left there is cleared or
- * overwritten before use), so calls that overlap on one GPU, from several
- * host threads or on several streams, race and are not supported.
+ * overwritten before use).  Calls from several host threads are serialised
+ * by the per-device lock, so they never overlap on the array.
  */
 #define RS_NOALLOC_SCRATCH_BYTES (128u << 20)
 int rs_fof3d_noalloc(const float* x, const float* y, const float* z, int64_t n, float box,

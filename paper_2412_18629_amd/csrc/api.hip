@@ -52,6 +52,8 @@ int rs_fof3d(const float* x, const float* y, const float* z, int64_t n, float bo
         if (n_groups) *n_groups = 0;
         return RS_OK;
     }
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::fof3d_run(x, y, z, n, box, link_len, labels, n_groups,
                          static_cast<hipStream_t>(stream));
@@ -68,6 +70,8 @@ int rs_fof3d_noalloc(const float* x, const float* y, const float* z, int64_t n, 
         if (n_groups) *n_groups = 0;
         return RS_OK;
     }
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     return rs::fof3d_noalloc_run(x, y, z, n, box, link_len, labels, n_groups,
                                  static_cast<hipStream_t>(stream));
 }
@@ -88,6 +92,8 @@ int rs_fof3d_subbox(const float* x, const float* y, const float* z, int64_t n, i
         if (n_links) *n_links = 0;
         return RS_OK;
     }
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::fof3d_subbox_run(x, y, z, n, n_owned, lo, hi, ghost_width, link_len, labels,
                                 ghost_links, n_links, static_cast<hipStream_t>(stream));
@@ -106,6 +112,8 @@ int rs_phase_fof_batch(const float* x, const float* y, const float* z, const flo
     if ((flags & 0xffu) == RS_LEARNED && !model) return RS_EINVAL;
     if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !fof_labels)) return RS_EINVAL;
     RS_TRY(rs::device_ready());
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin((1u << rs::AR_BASE) | (1u << rs::AR_LARGE) |
                                 (1u << rs::AR_TREE) | (1u << rs::AR_MLP)));
     return rs::phase_run(x, y, z, vx, vy, vz, n, box, fof_labels, min_group, min_sub, f, flags,
@@ -127,6 +135,8 @@ int rs_halo_props(const float* x, const float* y, const float* z, const float* v
     if (n == 0 && n_nodes > 0) return RS_EINVAL;   /* nodes without particles */
     RS_TRY(rs::device_ready());
     if (n == 0) return RS_OK;
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::props_run(x, y, z, vx, vy, vz, n, box, n_nodes, n_levels, level, parent,
                          min_index, size, deepest, props, static_cast<hipStream_t>(stream));
@@ -149,6 +159,8 @@ int rs_seed_assign(const float* x, const float* y, const float* z, const float* 
     if (n == 0 && n_nodes > 0) return RS_EINVAL;
     RS_TRY(rs::device_ready());
     if (n == 0) return RS_OK;
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin(1u << rs::AR_BASE));
     return rs::seeds_run(x, y, z, vx, vy, vz, n, box, n_nodes, n_levels, level, parent,
                          min_index, size, deepest, a, c, props, halo,
@@ -166,6 +178,8 @@ int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int
     if (n == 0) return RS_OK;
     rs::Arena* ar = nullptr;
     const size_t tb = rs::sort_temp_bytes(n);
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::arena_call_begin(1u << rs::AR_SORT));
     RS_TRY(rs::arena_reserve(rs::AR_SORT, tb, &ar));
     void* temp = rs::arena_take(ar, tb);
@@ -176,6 +190,8 @@ int rs_sort_pairs_u64_i32(const uint64_t* keys_in, uint64_t* keys_out, const int
 
 int rs_release_workspace(void) {
     RS_TRY(rs::device_ready());
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_HIP(hipDeviceSynchronize());
     for (int k = 0; k < rs::N_ARENAS; k++) RS_TRY(rs::arena_release(k));
     return RS_OK;

@@ -10,6 +10,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <mutex>
+
 #include "../../include/rsfof.h"
 
 #define RS_DEV __device__ __forceinline__
@@ -195,6 +197,9 @@ constexpr int AR_BASE = 0, AR_LARGE = 1, AR_MLP = 2, AR_SORT = 3, AR_TREE = 4;
 // device's other arenas (left by earlier calls of other phases) are
 // released and the allocation is tried again.
 int arena_call_begin(uint32_t keep_mask);
+// Serialises the library's calls on the current device (its workspaces are
+// per device): every entry point that uses them holds this lock.
+int call_lock(std::unique_lock<std::mutex>* lk);
 // device bytes the current call could obtain: free memory plus the arenas it
 // does not hold plus those in replace_mask (about to be re-reserved)
 int device_budget(uint32_t replace_mask, size_t* bytes);

@@ -270,6 +270,8 @@ int rs_mlp_grad(const float* params, const float* X, const float* T, int64_t n, 
     if (!params || !X || !T || !grad || !loss || n <= 0) return RS_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float *g, *l;
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::mlp_grad_impl(params, X, T, n, &g, &l, st));
     RS_HIP(hipMemcpyAsync(grad, g, 4 * rs::NPARAM, hipMemcpyDeviceToDevice, st));
     RS_HIP(hipMemcpyAsync(loss, l, 4, hipMemcpyDeviceToDevice, st));
@@ -283,6 +285,8 @@ int rs_mlp_train_step(float* params, float* m, float* v, int64_t step, const flo
         return RS_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float *g, *l;
+    std::unique_lock<std::mutex> lk;
+    RS_TRY(rs::call_lock(&lk));
     RS_TRY(rs::mlp_grad_impl(params, X, T, n, &g, &l, st));
     const float b1 = 0.9f, b2 = 0.999f;
     float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);

@@ -121,6 +121,9 @@ RS_DEV float mload(const float* __restrict__ base, int64_t m) {
         return base[m];
 }
 constexpr int64_t O32_LIMIT = (int64_t)1 << 30;
+// 32-bit member offsets below O32_LIMIT members; the test hook
+// RS_DEBUG_WIDE_OFFSETS selects the 64-bit form on any level
+bool use_o32(int64_t nmem);
 
 int tree_build(TreeBuf& tb, int32_t* root, const uint64_t* skeys, const LNode* nodes, int nv,
                const Members& T, const int32_t* mnode, const LParam* prm,

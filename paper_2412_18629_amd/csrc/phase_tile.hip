@@ -252,7 +252,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
 int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
     if (ntiles <= 0) return RS_OK;
     const int c = xcd_chunk(ntiles);
-    if (A.nmem < O32_LIMIT)
+    if (use_o32(A.nmem))
         k_tile_link<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);
     else
         k_tile_link<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);

@@ -646,7 +646,7 @@ int tree_refit_active(TreeBuf& tb, int32_t n_entry, const std::vector<int32_t>& 
 
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st) {
     const int c = xcd_chunk(ntiles);
-    if (A.nmem < O32_LIMIT)
+    if (use_o32(A.nmem))
         k_tree_nn<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
     else
         k_tree_nn<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);

@@ -1,7 +1,8 @@
 // prims.hip -- device-wide building blocks: exclusive scan, key/value sort,
 // fills, and the per-device workspace.
-#include "common.h"
+#include "phase_common.h"
 
+#include <stdlib.h>
 #include <string.h>
 
 
@@ -41,6 +42,10 @@ static TuneDef g_tune[TUNE_N] = {
 
 int tune_get(TuneKnob k) { return g_tune[k].value; }
 
+bool use_o32(int64_t nmem) {
+    return nmem < O32_LIMIT && !getenv("RS_DEBUG_WIDE_OFFSETS");
+}
+
 static int tune_find(const char* name) {
     if (!name) return -1;
     for (int k = 0; k < TUNE_N; k++)
@@ -51,6 +56,15 @@ static int tune_find(const char* name) {
 static int current_device(int* dev) {
     RS_HIP(hipGetDevice(dev));
     return (*dev < 0 || *dev >= 64) ? RS_EDEVICE : RS_OK;
+}
+
+static std::mutex g_call_mu[64];
+
+int call_lock(std::unique_lock<std::mutex>* lk) {
+    int dev = 0;
+    RS_TRY(current_device(&dev));
+    *lk = std::unique_lock<std::mutex>(g_call_mu[dev]);
+    return RS_OK;
 }
 
 int arena_call_begin(uint32_t keep_mask) {
@@ -104,6 +118,8 @@ int arena_reserve(int which, size_t bytes, Arena** out) {
     if (which < 0 || which >= N_ARENAS) return RS_EDEVICE;
     Arena* a = &g_arena[dev][which];
     if (a->cap < bytes) {
+        // test hook: a reservation that needs new device memory fails
+        if (getenv("RS_DEBUG_FAIL_ALLOC")) return RS_ENOMEM;
         if (a->base) {
             RS_HIP(hipFree(a->base));
             a->base = nullptr;
