@@ -46,6 +46,7 @@ def _load():
     i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
     lib.oracle_fof3d.argtypes = [P, P, P, i64, f32, f32, P]
     lib.oracle_fof3d_brute.argtypes = [P, P, P, i64, f32, f32, P]
+    lib.oracle_fof3d_mode.argtypes = [P, P, P, i64, f32, f32, ctypes.c_int, P]
     lib.oracle_phase_fof.argtypes = [P, P, P, P, P, P, i64, f32, P, i32, i32, f64, i64,
                                      i64, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_i128_to_f64.argtypes = [i64, ctypes.c_uint64]
@@ -73,14 +74,18 @@ class OracleError(RuntimeError):
     pass
 
 
-def fof3d(x, y, z, box, link_len, brute=False):
-    """3D FoF labels (smallest member index per group), int32[n]."""
+def fof3d(x, y, z, box, link_len, brute=False, grid="auto"):
+    """3D FoF labels (smallest member index per group), int32[n].  grid:
+    "auto" (small cells with same-cell linking where the box allows it),
+    "coarse" (cells of side >= ll, every member pair tested); brute=True
+    tests all pairs."""
     lib = _load()
     x, y, z = _f32(x), _f32(y), _f32(z)
     n = x.size
     lab = np.empty(n, dtype=np.int32)
-    fn = lib.oracle_fof3d_brute if brute else lib.oracle_fof3d
-    rc = fn(_ptr(x), _ptr(y), _ptr(z), n, float(box), float(link_len), _ptr(lab))
+    mode = 1 if brute else {"auto": 0, "coarse": 2}[grid]
+    rc = lib.oracle_fof3d_mode(_ptr(x), _ptr(y), _ptr(z), n, float(box), float(link_len), mode,
+                               _ptr(lab))
     if rc != 0:
         raise OracleError(f"oracle_fof3d failed: {rc}")
     return lab

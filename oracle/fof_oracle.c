@@ -172,11 +172,9 @@ static int64_t lower_key(const kv_t *s, int64_t m, int64_t k)
  * itself it is at least three quarters of the relative one, as nc >= 3
  * below).  Every pair with computed D <= ll^2 is visited.
  */
-int oracle_fof3d(const float *x, const float *y, const float *z,
-                 int64_t n, float L, float ll, int32_t *labels)
+static int fof3d_coarse(const float *x, const float *y, const float *z,
+                        int64_t n, float L, float ll, int32_t *labels)
 {
-    if (n < 0 || !(L > 0.0f) || !(ll > 0.0f)) return -1;
-    if (check_positions(x, y, z, n, L)) return -2;
     double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + (double)L * ldexp(1.0, -22);
     int64_t nc = (int64_t)floor((double)L / side_min);
     if (nc < 3 || nc > 2000000) return oracle_fof3d_brute(x, y, z, n, L, ll, labels);
@@ -223,6 +221,137 @@ int oracle_fof3d(const float *x, const float *y, const float *z,
     free(s);
     free(parent);
     return 0;
+}
+
+
+/*
+ * Periodic grid of small cells, side s = L / nc <= ll / sqrt(3 (1 + 1e-5)):
+ * two particles of one cell are closer than the cell diagonal sqrt(3) s, so
+ * their computed D <= ll^2 (the 1e-5 covers the rounding of the differences,
+ * squares and sums, and of the fp64 cell assignment), and every particle of
+ * a cell is linked to the cell's first one without a test.  A pair whose
+ * computed D <= ll^2 has a true separation below ll (1 + 2^-22) + L 2^-24 on
+ * every axis (the face argument of the coarse grid), so its cells are at most
+ * r = floor((ll (1 + 2^-20) + L 2^-22) / s) + 1 apart per axis: each pair of
+ * occupied cells within r is visited once, skipped when the two cells are
+ * already one component, and otherwise linked at the first member pair with
+ * D <= ll^2 (the two cells are each one component, so one link joins them).
+ * Rows of cells (fixed y, z) are runs of the x-fastest keys, found through a
+ * table of row starts.
+ */
+static int fof3d_fine(const float *x, const float *y, const float *z, int64_t n, float L,
+                      float ll, int64_t nc, int64_t r, int32_t *labels)
+{
+    float h = 0.5f * L, ll2 = ll * ll;
+    double scale = (double)nc / (double)L;
+    kv_t *s = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *rowstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc * nc + 1));
+    if (!s || !parent || !rowstart) { free(s); free(parent); free(rowstart); return -3; }
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c[3];
+        double u[3] = { (double)x[i] * scale, (double)y[i] * scale, (double)z[i] * scale };
+        for (int a = 0; a < 3; a++) {
+            c[a] = (int64_t)floor(u[a]);
+            if (c[a] >= nc) c[a] = nc - 1;
+            if (c[a] < 0) c[a] = 0;
+        }
+        s[i].key = (c[2] * nc + c[1]) * nc + c[0];
+        s[i].idx = i;
+        parent[i] = i;
+    }
+    qsort(s, (size_t)n, sizeof(kv_t), cmp_kv);
+    /* cells: runs of equal keys; every member joins the cell's first member */
+    int64_t ncell = 0;
+    for (int64_t p = 0; p < n; p++)
+        if (p == 0 || s[p].key != s[p - 1].key) ncell++;
+    int64_t *cfirst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell + 1));
+    int64_t *ckey = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    if (!cfirst || !ckey) {
+        free(s); free(parent); free(rowstart); free(cfirst); free(ckey);
+        return -3;
+    }
+    int64_t k = 0;
+    for (int64_t p = 0; p < n; p++) {
+        if (p == 0 || s[p].key != s[p - 1].key) {
+            cfirst[k] = p;
+            ckey[k] = s[p].key;
+            k++;
+        } else {
+            uf_union(parent, s[cfirst[k - 1]].idx, s[p].idx);
+        }
+    }
+    cfirst[ncell] = n;
+    /* rowstart[R] = first cell whose key is >= R nc */
+    for (int64_t R = 0, c = 0; R <= nc * nc; R++) {
+        while (c < ncell && ckey[c] < R * nc) c++;
+        rowstart[R] = c;
+    }
+    for (int64_t a = 0; a < ncell; a++) {
+        int64_t key = ckey[a];
+        int64_t cx = key % nc, cy = (key / nc) % nc, cz = key / (nc * nc);
+        int64_t pa = s[cfirst[a]].idx;
+        for (int64_t dz = -r; dz <= r; dz++)
+        for (int64_t dy = -r; dy <= r; dy++) {
+            int64_t oy = (cy + dy + nc) % nc, oz = (cz + dz + nc) % nc;
+            int64_t R = oz * nc + oy;
+            for (int64_t b = rowstart[R]; b < rowstart[R + 1]; b++) {
+                if (ckey[b] <= key) continue;               /* each cell pair once */
+                int64_t ox = ckey[b] - R * nc;
+                int64_t dxc = ox - cx;
+                if (dxc > nc / 2) dxc -= nc;                /* x offset, nearest image */
+                else if (dxc < -(nc / 2)) dxc += nc;
+                if (dxc < -r || dxc > r) continue;
+                int64_t pb = s[cfirst[b]].idx;
+                if (uf_find(parent, pa) == uf_find(parent, pb)) continue;
+                int found = 0;
+                for (int64_t p = cfirst[a]; p < cfirst[a + 1] && !found; p++)
+                    for (int64_t q = cfirst[b]; q < cfirst[b + 1]; q++)
+                        if (pos_d2(x, y, z, s[p].idx, s[q].idx, L, h) <= ll2) {
+                            found = 1;
+                            break;
+                        }
+                if (found) uf_union(parent, pa, pb);
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
+    free(s); free(parent); free(rowstart); free(cfirst); free(ckey);
+    return 0;
+}
+
+/*
+ * 3D FoF of a periodic box.  mode 0: the small-cell grid with same-cell
+ * linking where the grid allows it (at least 2r + 1 cells per axis and a
+ * row table of at most 2^26 rows), else the coarse grid; 1: all pairs;
+ * 2: the coarse grid (cells of side >= ll, every member pair of
+ * neighbouring cells tested).
+ */
+int oracle_fof3d_mode(const float *x, const float *y, const float *z,
+                      int64_t n, float L, float ll, int mode, int32_t *labels)
+{
+    if (n < 0 || !(L > 0.0f) || !(ll > 0.0f)) return -1;
+    if (check_positions(x, y, z, n, L)) return -2;
+    if (mode == 1) return oracle_fof3d_brute(x, y, z, n, L, ll, labels);
+    if (mode == 0) {
+        double smax = (double)ll / sqrt(3.0 * (1.0 + 1e-5));
+        double cnt = ceil((double)L / smax);
+        if (cnt <= 1048576.0) {
+            int64_t nc = (int64_t)cnt;
+            double side = (double)L / (double)nc;
+            int64_t r = (int64_t)floor(((double)ll * (1.0 + ldexp(1.0, -20)) +
+                                        (double)L * ldexp(1.0, -22)) / side) + 1;
+            if (nc >= 2 * r + 1 && nc * nc <= ((int64_t)1 << 26))
+                return fof3d_fine(x, y, z, n, L, ll, nc, r, labels);
+        }
+    }
+    return fof3d_coarse(x, y, z, n, L, ll, labels);
+}
+
+int oracle_fof3d(const float *x, const float *y, const float *z,
+                 int64_t n, float L, float ll, int32_t *labels)
+{
+    return oracle_fof3d_mode(x, y, z, n, L, ll, 0, labels);
 }
 
 /* ------------------------------------------------------------------ */

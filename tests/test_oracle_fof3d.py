@@ -195,6 +195,7 @@ def test_grid_margin_edge_pairs(L, counts, plain):
         x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
         ref = brute.fof3d(x, y, z, L, ll)
         assert np.array_equal(oracle.fof3d(x, y, z, L, ll), ref), (L, ll)
+        assert np.array_equal(oracle.fof3d(x, y, z, L, ll, grid="coarse"), ref), (L, ll)
         assert np.array_equal(oracle.fof3d(x, y, z, L, ll, brute=True), ref), (L, ll)
         sep = ep.true_separation(pos, pairs, L)
         linked = ref[pairs[:, 0]] == ref[pairs[:, 1]]
@@ -203,3 +204,47 @@ def test_grid_margin_edge_pairs(L, counts, plain):
     # the rounding of the image shift decides some pairs either way: the
     # construction reaches the cases the margin is about
     assert rounded_in > 0 or rounded_out > 0
+
+
+@pytest.mark.parametrize("L,ll", [(20.0, 0.2), (320.0, 0.175), (17.0, 0.5)])
+def test_same_cell_linking_stays_inside_ll(L, ll):
+    # for every cell count a small-cell grid could plausibly use (around
+    # L sqrt(3) / ll), pairs along the diagonal of its cells, from a corner,
+    # separated by between 0.995 ll and the cell's diagonal (or 1.005 ll):
+    # whichever of these grids the oracle uses, same-cell linking may only
+    # join pairs the pair test joins (a cell whose diagonal exceeds ll would
+    # link pairs farther apart than ll)
+    L, ll = F32(L), F32(ll)
+    rng = np.random.default_rng(int(L))
+    pts = []
+    n0 = int(round(float(L) * np.sqrt(3.0) / float(ll)))
+    for nc in range(n0 - 2, n0 + 3):
+        side = float(L) / nc
+        top = max(side * np.sqrt(3.0) / float(ll), 1.005)
+        for f in np.linspace(0.995, top, 24):
+            c = rng.integers(2, nc - 3, 3)
+            p = c * side + 2e-6 * side
+            pts += [p, p + float(ll) * f / np.sqrt(3.0)]
+    pos = np.array(pts).astype(F32)
+    x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+    ref = brute.fof3d(x, y, z, L, ll)
+    assert np.array_equal(oracle.fof3d(x, y, z, L, ll), ref)
+    linked = ref[0::2] == ref[1::2]
+    assert linked.any() and not linked.all()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_dense_clumps_fine_and_coarse_grids(seed):
+    # dense cores (many particles per small cell): same-cell linking and the
+    # early exit between cells against the coarse grid and all pairs
+    rng = np.random.default_rng(40 + seed)
+    L = F32(10.0)
+    cen = rng.random((6, 3)) * 10
+    pos = np.mod(cen[rng.integers(0, 6, 3000)] + rng.normal(0, 0.05 + 0.1 * seed, (3000, 3)),
+                 10.0).astype(F32)
+    pos[pos >= L] = 0
+    ll = F32(0.1)
+    x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+    ref = brute.fof3d(x, y, z, L, ll)
+    assert np.array_equal(oracle.fof3d(x, y, z, L, ll), ref)
+    assert np.array_equal(oracle.fof3d(x, y, z, L, ll, grid="coarse"), ref)
