@@ -12,6 +12,7 @@ R is a dict of host arrays:
   props, halo   (optional) rs_halo_props rows [15, nodes] and rs_seed_assign [n]
 """
 from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import TimeoutError as FuturesTimeout
 
 import numpy as np
 
@@ -133,6 +134,19 @@ def stratified(sizes, groups, n_pick, min_group, seed=0):
     return groups[np.concatenate(pick)]
 
 
+def _gather(ex, futs, what, log):
+    """Results of the futures in order, with a progress line every 30 s."""
+    out = []
+    for k, f in enumerate(futs):
+        while True:
+            try:
+                out.append(f.result(timeout=30))
+                break
+            except FuturesTimeout:
+                log(f"{what} checks: {k} of {len(futs)} done")
+    return out
+
+
 def check_all(R, cfg, n_sample=64, subtree_max=150000, closure_max=None, log=print):
     """Structural invariants of the whole tree, level-0 moments of every
     group, 3D closure of sampled groups (up to closure_max members when
@@ -197,13 +211,14 @@ def check_all(R, cfg, n_sample=64, subtree_max=150000, closure_max=None, log=pri
         f"{sorted(cnt[pick].tolist())}")
     pick3 = [g for g in pick if closure_max is None or cnt[g] <= closure_max]
     with ThreadPoolExecutor(WORKERS) as ex:
-        r3 = list(ex.map(lambda g: check_3d(R, cfg, g), pick3))
+        r3 = _gather(ex, [ex.submit(check_3d, R, cfg, g) for g in pick3], "3D closure", log)
     bad3 = [(g, s, r) for ok, g, s, r in r3 if not ok]
     assert not bad3, bad3
     deep = [g for g in pick if subtree_max is None or cnt[g] <= subtree_max]
     deep.sort(key=lambda g: -cnt[g])          # largest first on the pool
     with ThreadPoolExecutor(WORKERS) as ex:
-        r6 = list(ex.map(lambda g: check_subtree(R, cfg, g, root_of, canon_root), deep))
+        r6 = _gather(ex, [ex.submit(check_subtree, R, cfg, g, root_of, canon_root)
+                          for g in deep], "6D subtree", log)
     bad6 = [b for r in r6 for b in r]
     assert not bad6, bad6[:10]
     log(f"{cfg.name}: 3D checked on {len(pick3)} groups (largest {max(cnt[g] for g in pick3)}), "
