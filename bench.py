@@ -104,19 +104,24 @@ def _kernel_values(rows, kernel):
     return out
 
 
-# vector ALU: 256 CUs x 4 SIMDs of 16 lanes; a wave64 VALU instruction
-# occupies its SIMD for at least 4 cycles.  SQ_INSTS_VALU counts the VALU
+# vector ALU: 256 CUs x 4 SIMDs of 16 lanes, so a full wave64 VALU
+# instruction occupies its SIMD for 4 cycles.  SQ_INSTS_VALU counts the VALU
 # instructions the wavefronts issued; GRBM_GUI_ACTIVE is the busy cycles,
-# summed over the 8 XCDs.  The busy fraction is then a lower bound (64-bit
-# and transcendental instructions take longer) that cannot exceed 1.
+# summed over the 8 XCDs (per XCD it matches the kernel's duration at the
+# shader clock).  Charging every counted instruction 4 cycles gives the
+# issue density: 1.0 means one VALU instruction per SIMD every 4 cycles.
+# It is not a strict utilisation: instructions that read one lane into a
+# scalar register, or run with few lanes enabled, are counted but take
+# fewer cycles, so a saturated kernel can read slightly above 1.
 N_SIMD = 1024
 N_XCD = 8
 VALU_CYCLES = 4
 
 
 def valu_busy(insts, gui_active):
-    """Fraction of the vector-ALU issue cycles used, from SQ_INSTS_VALU and
-    GRBM_GUI_ACTIVE summed over a kernel's dispatches."""
+    """VALU issue density (4 cycles charged per counted instruction, over
+    every SIMD's cycles) from SQ_INSTS_VALU and GRBM_GUI_ACTIVE summed over a
+    kernel's dispatches."""
     if insts <= 0 or gui_active <= 0:
         return None
     return insts * VALU_CYCLES / (gui_active / N_XCD * N_SIMD)

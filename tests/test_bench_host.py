@@ -102,8 +102,8 @@ def test_workload_description_names_the_cube():
     assert "(1000001)" in bench.workload_description(odd)
 
 
-def test_valu_busy_is_a_fraction():
-    # every SIMD issuing a 4-cycle instruction each 4 cycles is the ceiling
+def test_valu_issue_density():
+    # every SIMD issuing a 4-cycle instruction each 4 cycles reads 1
     cycles = 1.0e6
     full = bench.N_SIMD * cycles / bench.VALU_CYCLES
     assert bench.valu_busy(full, cycles * bench.N_XCD) == pytest.approx(1.0)
