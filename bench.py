@@ -50,6 +50,14 @@ SMALL_BYTES = 32.0
 SMALL_MAX = 2048
 # halo properties: one 24-byte record read per member of every node
 PROPS_BYTES = 24.0
+# seed assignment: one (particle, seed) test is d^2 = fl(fl(a Dx) + fl(c Dv)),
+# 19 fp32 adds, subtracts and multiplies (3 + 3 differences, 3 + 3 squares,
+# 2 + 2 sums, 2 scalings, 1 sum); no FMA by definition and no packed
+# arithmetic, so the bound is the plain vector ALU rate: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3 T operations/s (the 157.3 TFLOP/s fp32 figure
+# counts a packed FMA as four)
+SEED_FLOPS = 19.0
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 FLAGS = {"learned": rs.RS_LEARNED, "batched": rs.RS_BATCHED, "plain": rs.RS_PLAIN}
 
 # device symbol and source files of each instrumented kernel (the PMC summary
@@ -239,8 +247,68 @@ def small_node_stats(tree, prof_small, steps):
             "note": "side streams, overlapped with the main-stream levels"}
 
 
+def seed_tests(tree):
+    """(particle, seed) tests of rs_seed_assign on a tree: every own particle
+    of a node with children against every seed (leaf) below that node."""
+    level, parent = tree["level"].long(), tree["parent"].long()
+    deepest = tree["deepest"].long()
+    m = level.numel()
+    if m == 0:
+        return 0
+    childsum = torch.bincount(parent[parent >= 0], minlength=m)
+    leafcnt = (childsum == 0).long()
+    for lv in range(int(level.max().item()), 0, -1):   # children before parents
+        at = torch.nonzero(level == lv).squeeze(1)
+        leafcnt.index_add_(0, parent[at], leafcnt[at])
+    own = torch.bincount(deepest[deepest >= 0], minlength=m)
+    has = childsum > 0
+    return int((own[has] * leafcnt[has]).sum().item())
+
+
+def subbox_row(arrs, cfg, reps=3):
+    """rs_fof3d_subbox on one process's share of an 8-way decomposition: the
+    cube [gw, gw + L/2)^3 with its ghost shell of width gw = 1.5 ll, selected
+    on the device with the sub-box's own fp32 bounds."""
+    gw = 1.5 * cfg.link_len
+    side = cfg.box / 2.0
+    lo32 = torch.full((3,), gw, dtype=torch.float32)
+    hi32 = (torch.full((3,), gw, dtype=torch.float64) + side).float()
+    gw64 = float(np.float32(gw))
+    x, y, z = arrs[0], arrs[1], arrs[2]
+    owned = torch.ones_like(x, dtype=torch.bool)
+    shell = torch.ones_like(x, dtype=torch.bool)
+    for a, c in enumerate((x, y, z)):
+        l, h = float(lo32[a]), float(hi32[a])
+        owned &= (c >= l) & (c < h)
+        c64 = c.double()
+        shell &= (c64 >= l - gw64) & (c64 < h + gw64)
+    idx = torch.cat([torch.nonzero(owned).squeeze(1), torch.nonzero(shell & ~owned).squeeze(1)])
+    sx, sy, sz = (c[idx].contiguous() for c in (x, y, z))
+    n_owned = int(owned.sum().item())
+    del owned, shell, idx
+    labels = torch.empty(sx.numel(), dtype=torch.int32, device=sx.device)
+    call = lambda: rs.rs_fof3d_subbox(sx, sy, sz, n_owned, lo32.tolist(), hi32.tolist(), gw,
+                                      cfg.link_len, labels=labels)
+    call()
+    rs.rs_profile_enable(False)
+    rs.rs_profile_enable(True)
+    ms, (_, links) = timed(call, reps)
+    tot, launches, units = rs.rs_profile_get("fof3d_link")
+    rs.rs_profile_enable(False)
+    avg = tot / max(launches, 1)
+    per = KERNEL_BYTES["fof3d_link"] * units / max(launches, 1)
+    gbs = per / (avg / 1000.0) / 1e9 if avg > 0 else 0.0
+    return {"cube": [float(lo32[0]), float(hi32[0])], "owned": n_owned,
+            "ghosts": int(sx.numel()) - n_owned, "ghost_links": int(links.shape[0]),
+            "ms_per_call": ms, "owned_per_s": n_owned / (ms / 1000.0),
+            "roofline": {"bound": "hbm", "kernel": "fof3d_link", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per}}
+
+
 def hierarchy_rows(arrs, cfg, tree, reps=3):
-    """Halo properties and seed assignment over the last step's hierarchy."""
+    """Halo properties and seed assignment over the last step's hierarchy,
+    and the sub-box pass on one eighth of the box."""
     props = rs.rs_halo_props(*arrs, cfg.box, tree)
     halo = rs.rs_seed_assign(*arrs, cfg.box, tree, props)
     torch.cuda.synchronize()
@@ -254,6 +322,9 @@ def hierarchy_rows(arrs, cfg, tree, reps=3):
     per = PROPS_BYTES * units / max(launches, 1)
     gbs = per / (avg / 1000.0) / 1e9 if avg > 0 else 0.0
     traffic = measured_pmc("halo_props", cfg.name, "hbm_bytes_per_launch")
+    tests = seed_tests(tree)
+    sk = st / max(sl, 1)
+    tflops = SEED_FLOPS * tests / (sk / 1000.0) / 1e12 if sk > 0 else 0.0
     return {
         "halo_props": {"ms_per_call": ms_p, "nodes": int(tree["level"].numel()),
                        "roofline": {"bound": "hbm", "kernel": "halo_props", "achieved": gbs,
@@ -262,8 +333,14 @@ def hierarchy_rows(arrs, cfg, tree, reps=3):
                                     "avg_launch_ms": avg,
                                     "algorithmic_bytes_per_launch": per,
                                     "member_levels": units / max(launches, 1)}},
-        "seed_assign": {"ms_per_call": ms_s, "kernel_ms": st / max(sl, 1),
-                        "assigned": int((halo >= 0).sum().item())},
+        "seed_assign": {"ms_per_call": ms_s, "kernel_ms": sk,
+                        "assigned": int((halo >= 0).sum().item()),
+                        "roofline": {"bound": "alu", "kernel": "seed_assign",
+                                     "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS,
+                                     "tests_per_call": tests,
+                                     "flops_per_test": SEED_FLOPS}},
+        "subbox": subbox_row(arrs, cfg, reps),
     }
 
 
@@ -282,9 +359,14 @@ def cpu_baseline(arrs, cfg, target=1100000, workers=None):
     gw = 1.5 * cfg.link_len
     sub, no, lo, hi = baseline.cut(host, (gw, gw, gw), side, gw)
     del host
-    no, nt, t3, t6, lab = baseline.run_one((sub, no, lo, hi, gw, cfg.box, cfg.link_len,
-                                            cfg.min_group, cfg.min_sub, cfg.f))
+    no, nt, t3, t6, lab, rows = baseline.run_one((sub, no, lo, hi, gw, cfg.box, cfg.link_len,
+                                                  cfg.min_group, cfg.min_sub, cfg.f))
     progress(f"oracle on one sub-box: {t3:.1f} s 3D + {t6:.1f} s 6D")
+    (tp, ml), (ts, npart) = rows["halo_props"], rows["seed_assign"]
+    row_rates = {"subbox": {"value": no / t3, "unit": "owned particles/s", "seconds": t3},
+                 "halo_props": {"value": ml / tp, "unit": "member-levels/s", "seconds": tp,
+                                "member_levels": ml},
+                 "seed_assign": {"value": npart / ts, "unit": "particles/s", "seconds": ts}}
     ncpu = os.cpu_count() or 1
     workers = workers or max(1, min(16, ncpu))
     parts = baseline.split_groups(sub, lab, cfg.min_group, workers)
@@ -296,6 +378,7 @@ def cpu_baseline(arrs, cfg, target=1100000, workers=None):
                        f"[{lo[0]:.3f}, {hi[0]:.3f})^3 Mpc/h, {no} owned particles and "
                        f"{nt - no} ghosts in a {gw:.4g} Mpc/h shell; sub-box 3D FoF "
                        f"{t3:.2f} s + 6D hierarchy {t6:.2f} s, single-threaded"),
+            "rows": row_rates,
             "all_core": {"value": no / (t3 + slowest), "unit": "particles/s",
                          "cores": workers, "host_cpus": ncpu, "kind": "oracle",
                          "sample": (f"the same sub-box: 3D FoF {t3:.2f} s single-threaded, "
@@ -414,6 +497,16 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(arrs, cfg)
         progress("oracle baseline timed")
+        if "hierarchy_rows" in line:
+            # the oracle's rate on the same sub-box beside each row's GPU rate
+            rr = line["hierarchy_rows"]
+            gpu = {"subbox": rr["subbox"]["owned_per_s"],
+                   "halo_props": (rr["halo_props"]["roofline"]["member_levels"] /
+                                  (rr["halo_props"]["ms_per_call"] / 1000.0)),
+                   "seed_assign": cfg.n / (rr["seed_assign"]["ms_per_call"] / 1000.0)}
+            for k, v in line["cpu_baseline"]["rows"].items():
+                rr[k]["oracle_1core"] = v
+                rr[k]["gpu_over_oracle"] = gpu[k] / v["value"]
     if args.probe_copy > 0:
         src = torch.ones(args.probe_copy * (1 << 18), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY (the benchmark's CPU-baseline leg).  It holds none
 of the method's arithmetic: it cuts one process's sub-box (owned particles
 plus the ghost shell of width gw, no periodic images needed for a cube away
 from the box faces) out of the workload arrays, then times the oracle's
-sub-box 3D FoF and its 6D hierarchy of the resulting groups (positions
-passed in their original periodic frame).  `run_parts` deals the groups of
+sub-box 3D FoF, its 6D hierarchy of the resulting groups (positions
+passed in their original periodic frame), and the halo properties and seed
+assignment of that hierarchy.  `run_parts` deals the groups of
 one sub-box to worker processes (fresh interpreters, so they never inherit a
 GPU context), one per core, and times their 6D hierarchies at once.
 """
@@ -44,15 +45,22 @@ def cut(arrs, lo, side, gw):
 def run_one(job):
     """Times the oracle on one sub-box: job = (arrays, n_owned, lo, hi, gw,
     box, link_len, min_group, min_sub, f).  Returns (n_owned, n, t3d, t6d,
-    labels)."""
+    labels, rows) with rows = {"halo_props": (seconds, member-levels),
+    "seed_assign": (seconds, particles)} over the sub-box's hierarchy."""
     import oracle
     arrs, n_owned, lo, hi, gw, box, ll, min_group, min_sub, f = job
     t0 = time.perf_counter()
     lab, _ = oracle.fof3d_subbox(arrs[0], arrs[1], arrs[2], n_owned, lo, hi, gw, ll)
     t1 = time.perf_counter()
-    oracle.phase_fof(*arrs, box, lab, min_group, min_sub, f)
+    t = oracle.phase_fof(*arrs, box, lab, min_group, min_sub, f)
     t2 = time.perf_counter()
-    return n_owned, arrs[0].size, t1 - t0, t2 - t1, lab
+    P = oracle.halo_props(*arrs, box, t["parent"], t["min_index"], t["deepest"])
+    t3 = time.perf_counter()
+    oracle.seed_assign(*arrs, box, t["parent"], t["deepest"], t["a"], t["c"], P)
+    t4 = time.perf_counter()
+    rows = {"halo_props": (t3 - t2, int(np.asarray(t["size"], np.int64).sum())),
+            "seed_assign": (t4 - t3, int(arrs[0].size))}
+    return n_owned, arrs[0].size, t1 - t0, t2 - t1, lab, rows
 
 
 def split_groups(arrs, labels, min_group, parts):

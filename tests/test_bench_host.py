@@ -121,3 +121,31 @@ def test_small_node_stats_count_subtree_roots():
     assert st["members_loaded"] == 540 and st["member_levels"] == 640
     assert st["ms_per_step"] == 10.0 and st["launches_per_step"] == 1.5
     assert st["achieved_gbs"] == pytest.approx(32.0 * 540 / 0.01 / 1e9)
+
+
+def test_seed_tests_counts_pairs_of_own_particles_and_seeds_below():
+    # the oracle's hierarchy of a small workload: every particle whose
+    # deepest node has children is tested against each leaf below that node
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2412_18629_amd import synth
+    cfg = synth.scaled(synth.CONFIGS["c32"], 6000)
+    h = [a.numpy() for a in synth.generate(cfg, 3)]
+    lab = oracle.fof3d(*h[:3], cfg.box, cfg.link_len)
+    t = oracle.phase_fof(*h, cfg.box, lab)
+    parent, deepest = t["parent"], t["deepest"]
+    m = parent.size
+    children = [[] for _ in range(m)]
+    for r in range(m):
+        if parent[r] >= 0:
+            children[parent[r]].append(r)
+
+    def leaves(r):
+        return 1 if not children[r] else sum(leaves(c) for c in children[r])
+
+    want = sum(leaves(d) for d in deepest if d >= 0 and children[d])
+    assert want > 0
+    tree = {k: torch.from_numpy(np.asarray(t[k])) for k in ("level", "parent", "deepest")}
+    assert bench.seed_tests(tree) == want
