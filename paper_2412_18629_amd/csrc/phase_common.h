@@ -60,6 +60,7 @@ struct LNode {              // one large node of the current level
     int64_t in_off;         // first member in the input buffer
     int64_t t_off;          // first member in tile order
     int32_t tile0, ntile, super0, nsuper;
+    int32_t item0, nitem;   // first (node, chunk) work item, and their count
 };
 
 struct LItem {              // (node, chunk) work item

@@ -769,16 +769,48 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
 
 // One level over the large nodes `hn` (host copies) whose members live in
 // `in`.  Appends the next level's large nodes to `next` (offsets into w->SN).
+// the last node whose first index (field F, ascending over the nodes) is at
+// most i
+template <int32_t LNode::*F>
+RS_DEV int32_t node_of(const LNode* __restrict__ nodes, int32_t nv, int32_t i) {
+    int32_t lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (nodes[mid].*F <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the level's tile -> node and super-tile -> node maps and its (node, chunk)
+// work items of up to LCHUNK members, built from the node table
+constexpr int32_t LCHUNK = 4096;
+
+__global__ void k_lmaps(int32_t nv, const LNode* __restrict__ nodes, int32_t tiles,
+                        int32_t supers, int32_t ni, int32_t* __restrict__ tile_node,
+                        int32_t* __restrict__ super_node, LItem* __restrict__ items) {
+    const int32_t n = max(tiles, max(supers, ni));
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x) {
+        if (i < tiles) tile_node[i] = node_of<&LNode::tile0>(nodes, nv, i);
+        if (i < supers) super_node[i] = node_of<&LNode::super0>(nodes, nv, i);
+        if (i < ni) {
+            const int32_t v = node_of<&LNode::item0>(nodes, nv, i);
+            const LNode nd = nodes[v];
+            const int64_t c = (int64_t)(i - nd.item0) * LCHUNK;
+            const int32_t len = (int32_t)min((int64_t)LCHUNK, (int64_t)nd.size - c);
+            items[i] = LItem{v, len, nd.in_off + c, nd.t_off + c};
+        }
+    }
+}
+
 int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
                 const float* X, const float* Y, const float* Z, const PhaseParams& pp,
                 const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
                 int64_t* n_accepted, int64_t* n_fallback, hipStream_t st) {
     const int nv = (int)hn.size();
     std::vector<LNode> nodes(nv);
-    std::vector<LItem> items;
-    std::vector<int32_t> tile_node, super_node;
     int64_t toff = 0;
-    int32_t tiles = 0, supers = 0;
+    int32_t tiles = 0, supers = 0, ni = 0;
     for (int v = 0; v < nv; v++) {
         LNode& nd = nodes[v];
         nd.slot = hn[v].slot;
@@ -789,29 +821,26 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
         nd.t_off = toff;
         nd.ntile = (nd.size + 63) / 64;
         nd.nsuper = (nd.ntile + 63) / 64;
+        nd.nitem = (int32_t)((nd.size + LCHUNK - 1) / LCHUNK);
         nd.tile0 = tiles;
         nd.super0 = supers;
-        for (int64_t c = 0; c < nd.size; c += 4096) {
-            int len = (int)(nd.size - c < 4096 ? nd.size - c : 4096);
-            items.push_back(LItem{v, len, nd.in_off + c, toff + c});
-        }
-        for (int k = 0; k < nd.ntile; k++) tile_node.push_back(v);
-        for (int k = 0; k < nd.nsuper; k++) super_node.push_back(v);
+        nd.item0 = ni;
         tiles += nd.ntile;
         supers += nd.nsuper;
+        ni += nd.nitem;
         toff += nd.size;
     }
     const int64_t M = toff;
-    if (nv > w->cap_nodes || (int64_t)items.size() > w->cap_items || tiles > w->cap_tiles ||
+    if (nv > w->cap_nodes || ni > w->cap_items || tiles > w->cap_tiles ||
         supers > w->cap_supers || M > w->cap_m)
         return RS_EINTERNAL;
-    const int ni = (int)items.size();
     RS_HIP(hipMemcpyAsync(w->nodes, nodes.data(), sizeof(LNode) * nv, hipMemcpyHostToDevice, st));
-    RS_HIP(hipMemcpyAsync(w->items, items.data(), sizeof(LItem) * ni, hipMemcpyHostToDevice, st));
-    RS_HIP(hipMemcpyAsync(w->tile_node, tile_node.data(), 4 * (size_t)tiles,
-                          hipMemcpyHostToDevice, st));
-    RS_HIP(hipMemcpyAsync(w->super_node, super_node.data(), 4 * (size_t)supers,
-                          hipMemcpyHostToDevice, st));
+    {
+        const int32_t nmap = std::max(tiles, std::max(supers, ni));
+        k_lmaps<<<grid_for(nmap, 256), 256, 0, st>>>(nv, w->nodes, tiles, supers, ni,
+                                                     w->tile_node, w->super_node, w->items);
+        RS_HIP(hipGetLastError());
+    }
     RS_HIP(hipMemsetAsync(w->gacc, 0, 8 * 18 * (size_t)nv, st));
     k_lext_init<<<grid_for(6 * nv, 256), 256, 0, st>>>(nv, w->gext);
     const int BT = 256;
