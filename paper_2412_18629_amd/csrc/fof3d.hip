@@ -188,12 +188,6 @@ RS_DEV void row_cells(const LinkArgs& A, uint64_t rr, int32_t& b, int32_t& e) {
     }
 }
 
-// test octant a (slots [s0, s1), octant bits oa) against every later octant
-// of cell c, which sits at offset (dx, dy, dz) cells from a's cell
-// `ra` is an element of a's component (its last known root): finding from it
-// is a short walk, and it is updated to the current root on every use.  With
-// auto-link the union-find runs over octant indices (one element per octant,
-// a dense array half the size of the slot array); otherwise over slots.
 // pair distance with the periodic shift (PER) or without (sub-box)
 template <bool PER>
 RS_DEV float link_d2(float xi, float yi, float zi, float xj, float yj, float zj,
@@ -202,24 +196,62 @@ RS_DEV float link_d2(float xi, float yi, float zi, float xj, float yj, float zj,
                : pos_d2_nowrap(xi, yi, zi, xj, yj, zj);
 }
 
+// test octant a (slots [s0, s1), octant bits oa) against every later octant
+// of cell c, which sits at offset (dx, dy, dz) cells from a's cell.
+// `ra` is an element of a's component (its last known root): finding from it
+// is a short walk; it is brought up to date once per batch of octants and
+// after each union (a stale one only costs a redundant test).  With
+// auto-link the union-find runs over octant indices (one element per octant,
+// a dense array half the size of the slot array); otherwise over slots.
+// The auto-linked pass takes the cell's octants in batches: their octant
+// bits and union-find parents are loaded together, so that the latencies
+// overlap instead of adding up along the thread's serial walk (the walk is
+// bound by them).
+constexpr int LINK_BATCH = 4;
+
 template <bool AUTOLINK, bool PER>
 RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int oa, int32_t c,
                       int dx, int dy, int dz, int32_t& ra) {
     const Grid3& g = A.g;
     const int32_t b0 = A.cell_oct[c], b1 = A.cell_oct[c + 1];
-    for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
-        if (g.octfilter) {
-            const int ob = A.oct_bits[b];
-            const int ddx = 2 * dx + (ob & 1) - (oa & 1);
-            const int ddy = 2 * dy + ((ob >> 1) & 1) - ((oa >> 1) & 1);
-            const int ddz = 2 * dz + (ob >> 2) - (oa >> 2);
-            if (ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 || ddz == -3)
-                continue;
+    // an octant pair is skipped when the filter puts it beyond reach
+    auto far = [&](int ob) {
+        const int ddx = 2 * dx + (ob & 1) - (oa & 1);
+        const int ddy = 2 * dy + ((ob >> 1) & 1) - ((oa >> 1) & 1);
+        const int ddz = 2 * dz + (ob >> 2) - (oa >> 2);
+        return ddx == 3 || ddx == -3 || ddy == 3 || ddy == -3 || ddz == 3 || ddz == -3;
+    };
+    if (!AUTOLINK) {
+        for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
+            if (g.octfilter && far(A.oct_bits[b])) continue;
+            const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
+            for (int32_t i = s0; i < s1; i++) {
+                const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
+                for (int32_t j = t0; j < t1; j++)
+                    if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2)
+                        uf_unite(A.parent, i, j);
+            }
         }
-        if (AUTOLINK) {
-            // every octant is one element: its members are linked already
-            ra = uf_find(A.parent, ra);
-            const int32_t rb = uf_find(A.parent, b);
+        return;
+    }
+    // every octant is one element: its members are linked already
+    for (int32_t base = b0 < a + 1 ? a + 1 : b0; base < b1; base += LINK_BATCH) {
+        int obk[LINK_BATCH];
+        int32_t pbk[LINK_BATCH];
+#pragma unroll
+        for (int k = 0; k < LINK_BATCH; k++) {
+            const int32_t b = base + k;
+            obk[k] = b < b1 ? A.oct_bits[b] : 0;
+            pbk[k] = b < b1 ? uf_load(A.parent, b) : 0;
+        }
+        ra = uf_find(A.parent, ra);
+#pragma unroll
+        for (int k = 0; k < LINK_BATCH; k++) {
+            const int32_t b = base + k;
+            if (b >= b1) break;
+            if (g.octfilter && far(obk[k])) continue;
+            // the root from the parent loaded above (parents only move up)
+            const int32_t rb = pbk[k] == b ? b : uf_find(A.parent, pbk[k]);
             if (ra == rb) continue;
             const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
             if ((int64_t)(s1 - s0) * (t1 - t0) > HEAVY_PAIRS) {
@@ -239,14 +271,9 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
                     }
                 }
             }
-            if (hit) uf_unite(A.parent, ra, rb);
-        } else {
-            const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
-            for (int32_t i = s0; i < s1; i++) {
-                const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
-                for (int32_t j = t0; j < t1; j++)
-                    if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2)
-                        uf_unite(A.parent, i, j);
+            if (hit) {
+                uf_unite(A.parent, ra, rb);
+                ra = uf_find(A.parent, ra);
             }
         }
     }
