@@ -250,8 +250,13 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             const int32_t b = base + k;
             if (b >= b1) break;
             if (g.octfilter && far(obk[k])) continue;
-            // the root from the parent loaded above (parents only move up)
+            // b hangs below a's root already, or its root is found from the
+            // parent loaded above (parents only move up) and stored as b's
+            // parent, so that the next octant to meet b reaches it at once
+            if (pbk[k] == ra) continue;
             const int32_t rb = pbk[k] == b ? b : uf_find(A.parent, pbk[k]);
+            if (rb != pbk[k] && rb != b)
+                __hip_atomic_store(A.parent + b, rb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (ra == rb) continue;
             const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
             if ((int64_t)(s1 - s0) * (t1 - t0) > HEAVY_PAIRS) {
