@@ -68,6 +68,14 @@ struct LItem {              // (node, chunk) work item
     int64_t in_start, t_start;
 };
 
+// a rejected bracket is refined in up to two steps.  Below lo: the queries
+// within lo are searched again with a stop at their first neighbour within
+// a lower threshold (REFINE_LO2 lo^2), exactly only when the k-th value lies
+// below it.  Above hi: the queries beyond hi are searched capped at
+// REFINE_CAP2 hi^2, without a cap only when the k-th value lies beyond it.
+constexpr float REFINE_LO2 = 0.81f;    // (0.9)^2
+constexpr float REFINE_CAP2 = 1.21f;   // (1.1)^2
+
 struct LParam {
     float a, c, sa, sc;
     float rx, ry, rz;       // reference member position
@@ -77,7 +85,8 @@ struct LParam {
     uint32_t pf, pm;        // radix-select prefix and mask
     int32_t kk;             // remaining rank
     float l2;
-    int32_t nnmode;         // 0 exact, 1 bracket, 2 done, 3/4 refine below lo / above hi
+    int32_t nnmode;         // 0 exact, 1 bracket, 2 done, 3/4 refine below lo / above hi,
+                            // 6/5 the second refinement step below / above
     float lo2, hi2;         // bracket (squares) when nnmode == 1
     float isx, isv;         // 1/sigma_x, 1/sigma_v for the feature histograms
 };

@@ -595,6 +595,44 @@ __global__ void k_laccept(int nv, const int32_t* __restrict__ lcnt, LParam* __re
     atomicAdd(lstat + (ok ? 0 : 1), 1);
 }
 
+// after the first refinement step: #(d = 0) of the nodes refined below lo,
+// #(d < +inf) of those refined above hi
+__global__ void __launch_bounds__(256)
+k_lcount_refine(const LItem* __restrict__ items, const float* __restrict__ d2,
+                const LParam* __restrict__ prm, int32_t* __restrict__ lcnt) {
+    __shared__ int32_t c;
+    const LItem it = items[blockIdx.x];
+    const int mode = prm[it.v].nnmode;
+    if (mode != 3 && mode != 4) return;
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    int b = 0;
+    for (int j = threadIdx.x; j < it.len; j += 256) {
+        const float d = d2[it.t_start + j];
+        b += mode == 3 ? d == 0.0f : d < __builtin_huge_valf();
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&c, b);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(lcnt + 2 * it.v + (mode == 3 ? 0 : 1), c);
+}
+
+// the refinement is complete when the k-th value lies in the band the first
+// step resolved exactly: #(d <= lo3) < k below lo, k <= #(d <= cap4) above
+// hi; otherwise the second step (modes 6, 5) searches the rest
+__global__ void k_laccept_refine(int nv, const int32_t* __restrict__ lcnt,
+                                 LParam* __restrict__ prm, int32_t* __restrict__ lstat) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int mode = prm[v].nnmode;
+    if (mode != 3 && mode != 4) return;
+    const int k = prm[v].kk;
+    const bool ok = mode == 3 ? lcnt[2 * v] < k : k <= lcnt[2 * v + 1];
+    prm[v].nnmode = ok ? 2 : (mode == 3 ? 6 : 5);
+    if (!ok) atomicAdd(lstat + 2, 1);
+}
+
 __global__ void k_lext_init(int nv, uint32_t* __restrict__ gext) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < 6 * nv) gext[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
@@ -906,6 +944,15 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
         if (hs[1] > 0) {
             prof_begin("phase_large_nn_fallback", st);
             RS_TRY(tree_nn(TA, tiles, w->d2, st));
+            // the first step's counts, from zero (the bracket's are spent)
+            RS_HIP(hipMemsetAsync(w->lcnt, 0, 4 * 2 * (size_t)nv, st));
+            k_lcount_refine<<<ni, 256, 0, st>>>(w->items, w->d2, w->prm, w->lcnt);
+            k_laccept_refine<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->lcnt, w->prm, w->lstat);
+            RS_HIP(hipGetLastError());
+            RS_HIP(hipMemcpyAsync(hs + 2, w->lstat + 2, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  st));
+            RS_HIP(hipStreamSynchronize(st));
+            if (hs[2] > 0) RS_TRY(tree_nn(TA, tiles, w->d2, st));
             prof_end("phase_large_nn_fallback", st, (double)M);
         }
     }

@@ -400,17 +400,30 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
     // bracket mode (1): searches are capped at hi^2 and stop at the first
     // neighbour within lo^2; the output encodes 0 = within lo, the exact d^2
     // in (lo^2, hi^2], +inf = nothing within hi.
-    // Refinement after a rejected bracket: the k-th smallest d^2 lies below
-    // lo^2 (mode 3: only queries coded 0 are searched, capped just above
-    // lo^2) or above hi^2 (mode 4: only queries coded +inf, uncapped); every
-    // other stored value already orders correctly against it.
-    const bool brk = P.nnmode == 1;
-    const float cap = brk ? __uint_as_float(__float_as_uint(P.hi2) + 1u)
-                    : P.nnmode == 3 ? __uint_as_float(__float_as_uint(P.lo2) + 1u)
-                                    : __builtin_huge_valf();
-    const float lo2 = brk ? P.lo2 : -1.0f;
-    const float redo = P.nnmode == 3 ? 0.0f : __builtin_huge_valf();
-    const bool refine = P.nnmode >= 3;
+    // Refinement after a rejected bracket searches only the queries that can
+    // hold the k-th smallest d^2; every other stored value already orders
+    // correctly against it.  Below lo^2: mode 3 searches the queries coded 0
+    // (capped just above lo^2) with a stop at the first neighbour within
+    // lo3 = REFINE_LO2 lo^2, coding 0 again there and the exact d^2 above;
+    // mode 6, when the k-th value lies within lo3 too, searches the queries
+    // still coded 0 exactly, capped just above lo3.  Above hi^2: mode 4
+    // searches the queries coded +inf capped at cap4 = REFINE_CAP2 hi^2
+    // (+inf beyond it); mode 5, when the k-th value lies beyond cap4 too,
+    // searches the queries still coded +inf without a cap.
+    const int mode = P.nnmode;
+    const bool brk = mode == 1;
+    const float cap4 = REFINE_CAP2 * P.hi2;
+    const float lo3 = REFINE_LO2 * P.lo2;
+    auto above = [](float v) { return __uint_as_float(__float_as_uint(v) + 1u); };
+    const float cap = brk ? above(P.hi2)
+                    : mode == 3 ? above(P.lo2)
+                    : mode == 4 ? above(cap4)
+                    : mode == 6 ? above(lo3)
+                                : __builtin_huge_valf();
+    // early stop: the first neighbour within this d^2 ends a query
+    const float lo2 = brk ? P.lo2 : mode == 3 ? lo3 : -1.0f;
+    const float redo = mode == 3 || mode == 6 ? 0.0f : __builtin_huge_valf();
+    const bool refine = mode >= 3;
     const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
     for (int64_t qm = ts; qm < te; qm++) {
         if (refine && !(d2out[qm] == redo)) continue;
@@ -554,6 +567,8 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
         if (lane == 0) {
             float out = best;
             if (brk) out = best <= lo2 ? 0.0f : (best <= P.hi2 ? best : __builtin_huge_valf());
+            else if (mode == 3 && best <= lo3) out = 0.0f;
+            else if (mode == 4 && !(best <= cap4)) out = __builtin_huge_valf();
             d2out[qm] = out;
         }
     }
