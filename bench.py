@@ -306,7 +306,7 @@ def subbox_row(arrs, cfg, reps=3):
                          "avg_launch_ms": avg, "algorithmic_bytes_per_launch": per}}
 
 
-def hierarchy_rows(arrs, cfg, tree, reps=3):
+def hierarchy_rows(arrs, cfg, tree, reps=3, subbox=True):
     """Halo properties and seed assignment over the last step's hierarchy,
     and the sub-box pass on one eighth of the box."""
     props = rs.rs_halo_props(*arrs, cfg.box, tree)
@@ -340,7 +340,7 @@ def hierarchy_rows(arrs, cfg, tree, reps=3):
                                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS,
                                      "tests_per_call": tests,
                                      "flops_per_test": SEED_FLOPS}},
-        "subbox": subbox_row(arrs, cfg, reps),
+        **({"subbox": subbox_row(arrs, cfg, reps)} if subbox else {}),
     }
 
 
@@ -397,7 +397,10 @@ def main():
     ap.add_argument("--no-speedup", action="store_true", help="skip the form comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-rows", action="store_true",
-                    help="skip the halo-property and seed-assignment timings")
+                    help="skip the halo-property, seed-assignment and sub-box timings")
+    ap.add_argument("--no-subbox", action="store_true",
+                    help="skip the sub-box timing (its 3D link launches would mix with the "
+                         "step's in a profile)")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 3 times (a plain "
                          "copy kernel of known size, for calibrating byte counters)")
@@ -489,7 +492,7 @@ def main():
     progress(f"{args.steps} steps at {ms:.1f} ms")
     line["small_node_kernels"] = small_node_stats(tree, prof_small, args.steps)
     if not args.no_rows:
-        line["hierarchy_rows"] = hierarchy_rows(arrs, cfg, tree)
+        line["hierarchy_rows"] = hierarchy_rows(arrs, cfg, tree, subbox=not args.no_subbox)
         progress("halo properties and seed assignment timed")
     if args.form == "learned" and not args.no_speedup:
         line["learned_speedup"] = speedups(arrs, cfg, labels, model, ms)
@@ -500,13 +503,15 @@ def main():
         if "hierarchy_rows" in line:
             # the oracle's rate on the same sub-box beside each row's GPU rate
             rr = line["hierarchy_rows"]
-            gpu = {"subbox": rr["subbox"]["owned_per_s"],
-                   "halo_props": (rr["halo_props"]["roofline"]["member_levels"] /
+            gpu = {"halo_props": (rr["halo_props"]["roofline"]["member_levels"] /
                                   (rr["halo_props"]["ms_per_call"] / 1000.0)),
                    "seed_assign": cfg.n / (rr["seed_assign"]["ms_per_call"] / 1000.0)}
+            if "subbox" in rr:
+                gpu["subbox"] = rr["subbox"]["owned_per_s"]
             for k, v in line["cpu_baseline"]["rows"].items():
-                rr[k]["oracle_1core"] = v
-                rr[k]["gpu_over_oracle"] = gpu[k] / v["value"]
+                if k in gpu:
+                    rr[k]["oracle_1core"] = v
+                    rr[k]["gpu_over_oracle"] = gpu[k] / v["value"]
     if args.probe_copy > 0:
         src = torch.ones(args.probe_copy * (1 << 18), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
