@@ -502,7 +502,8 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         // the large-node levels run on the caller's: they read the level-0
         // members only, write disjoint particles' deepest nodes and take node
         // record slots atomically, so the two overlap freely and the result
-        // does not depend on their interleaving.
+        // does not depend on their interleaving.  The percolation pass follows
+        // them there, away from the start of the first large-node level.
         hipStream_t s2 = nullptr;
         hipEvent_t ready = nullptr, done = nullptr;
         RS_TRY(side_stream(0, &s2, &ready, &done));
@@ -510,11 +511,12 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         lw.side_pending = false;
         RS_HIP(hipEventRecord(ready, st));
         RS_HIP(hipStreamWaitEvent(s2, ready, 0));
-        span_pass(s2);
-        int rc = hipGetLastError() == hipSuccess ? RS_OK : RS_EDEVICE;
+        int rc = RS_OK;
         for (int b = 3; b >= 0 && rc == RS_OK; b--)
             rc = run_small_bucket(b, buckets + b * bstride, bcnt[b], A, nr, pp, deepest, s2,
                                   "phase_small_level0");
+        span_pass(s2);
+        if (rc == RS_OK && hipGetLastError() != hipSuccess) rc = RS_EDEVICE;
         size_t li = 0;
         while (rc == RS_OK && li < large.size()) {
             std::vector<ChildOut> cur, nxt;

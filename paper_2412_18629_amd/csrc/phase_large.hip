@@ -404,7 +404,10 @@ __global__ void k_lstat(int64_t m, const int32_t* __restrict__ par,
         const int32_t lr = __shfl(r, leader, 64);
         const bool mine = active && r == lr;
         const uint64_t grp = __ballot(mine);
-        const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+        // a root held by one lane only (members that linked nothing in this
+        // wavefront, about a third of them) needs no reduction
+        const unsigned long long mn =
+            __popcll(grp) == 1 ? key : wave_min_u64(mine ? key : ~0ull);
         if ((int)(threadIdx.x & 63) == leader) {
             atomicAdd(cnt + lr, __popcll(grp));
             atomicMin(mpk + lr, mn);
