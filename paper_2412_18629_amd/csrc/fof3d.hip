@@ -415,7 +415,9 @@ __global__ void k_min_index(int64_t n, const int32_t* __restrict__ parent,
         const int32_t lr = __shfl(r, leader, 64);
         const bool mine = active && r == lr;
         const uint64_t grp = __ballot(mine);
-        const unsigned long long mn = wave_min_u64(mine ? key : ~0ull);
+        // a root held by one lane only needs no reduction
+        const unsigned long long mn =
+            __popcll(grp) == 1 ? key : wave_min_u64(mine ? key : ~0ull);
         if ((int)(threadIdx.x & 63) == leader) atomicMin(minidx + lr, (int32_t)mn);
         todo &= ~grp;
     }

@@ -634,7 +634,7 @@ int seeds_run(const float* x, const float* y, const float* z, const float* vx,
     auto add = [&](size_t b) { bytes += arena_round(b); };
     add(8 * (size_t)n); add(8 * (size_t)n);               // sort keys in / out
     add(4 * (size_t)n); add(4 * (size_t)n);               // index in / sorted
-    for (int k = 0; k < 11; k++) add(4 * ((size_t)m + 1)); // per-node tables
+    for (int k = 0; k < 10; k++) add(4 * ((size_t)m + 1)); // per-node tables
     add(sizeof(SeedRec) * ((size_t)m + 1));               // seed records
     add(4 * (size_t)cap_items);                           // item -> node
     add(4 * ((size_t)nlev + 2));                          // level starts
@@ -655,7 +655,6 @@ int seeds_run(const float* x, const float* y, const float* z, const float* vx,
     int32_t* nitem = take<int32_t>(ar, m + 1);
     int32_t* ioff = take<int32_t>(ar, m + 1);
     int32_t* seednode = take<int32_t>(ar, m + 1);
-    int32_t* spare = take<int32_t>(ar, m + 1);
     SeedRec* seeds = take<SeedRec>(ar, m + 1);
     int32_t* items = take<int32_t>(ar, cap_items);
     int32_t* lstart = take<int32_t>(ar, nlev + 2);
@@ -665,7 +664,6 @@ int seeds_run(const float* x, const float* y, const float* z, const float* vx,
     // counters: 0 err, 1 own total, 2 level-0 leaves, 3 items
     int32_t* ctr = take<int32_t>(ar, 16);
     if (!ctr) return RS_EINTERNAL;
-    (void)spare;
     int32_t* hc = nullptr;
     RS_TRY(host_scratch((void**)&hc, 64));
 
