@@ -808,8 +808,6 @@ int launch_small_items(LargeWork* w, const SmallItem* items, int n, const Member
     return RS_OK;
 }
 
-// One level over the large nodes `hn` (host copies) whose members live in
-// `in`.  Appends the next level's large nodes to `next` (offsets into w->SN).
 // the last node whose first index (field F, ascending over the nodes) is at
 // most i
 template <int32_t LNode::*F>
@@ -844,6 +842,8 @@ __global__ void k_lmaps(int32_t nv, const LNode* __restrict__ nodes, int32_t til
     }
 }
 
+// One level over the large nodes `hn` (host copies) whose members live in
+// `in`.  Appends the next level's large nodes to `next` (offsets into w->SN).
 int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in,
                 const float* X, const float* Y, const float* Z, const PhaseParams& pp,
                 const NodeRec& nr, int32_t* deepest, std::vector<ChildOut>* next,
