@@ -226,6 +226,22 @@ def speedups(arrs, cfg, labels, model, ms_learned):
             "plain_workload": cfg.name}
 
 
+def pair_tests(arrs, cfg, form, labels, model, kernel_ms):
+    """Pair tests of the searches, counted on one extra (untimed) step with
+    the counting kernel builds, per second of the timed step's kernels."""
+    rs.rs_profile_enable(False)
+    rs.rs_profile_enable(2)
+    one_step(arrs, cfg, form, labels, model)
+    torch.cuda.synchronize()
+    got = {k: rs.rs_profile_get(k)[2] for k in ("pairs_fof3d", "pairs_nn", "pairs_link")}
+    rs.rs_profile_enable(False)
+    ms = {"pairs_fof3d": kernel_ms["fof3d_link"],
+          "pairs_nn": kernel_ms["phase_large_nn"] + kernel_ms["phase_large_nn_fallback"],
+          "pairs_link": kernel_ms["phase_large_link"]}
+    return {k: {"pairs_per_step": v, "kernel_ms_per_step": ms[k],
+                "per_s": v / (ms[k] / 1000.0) if ms[k] > 0 else None} for k, v in got.items()}
+
+
 def small_node_stats(tree, prof_small, steps):
     """The small-node subtree kernels: members of the subtree roots they load
     (nodes of at most SMALL_MAX members whose parent is larger or absent) and
@@ -491,6 +507,9 @@ def main():
     }
     progress(f"{args.steps} steps at {ms:.1f} ms")
     line["small_node_kernels"] = small_node_stats(tree, prof_small, args.steps)
+    line["pair_tests"] = pair_tests(arrs, cfg, args.form, labels, model,
+                                    line["config"]["kernel_ms_per_step"])
+    progress("pair tests counted")
     if not args.no_rows:
         line["hierarchy_rows"] = hierarchy_rows(arrs, cfg, tree, subbox=not args.no_subbox)
         progress("halo properties and seed assignment timed")

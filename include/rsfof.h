@@ -316,6 +316,13 @@ int rs_mlp_infer(const float* model, int64_t n, const float* features, float* ou
  * "phase_large_nn_fallback", "halo_props", "seed_assign") and
  * accumulates their elapsed time, launch count and processed work units
  * (particles or node members).  rs_profile_enable(0) clears the records.
+ * rs_profile_enable(2) also counts the pair tests of the searches, reported
+ * as units of "pairs_fof3d" (member pairs of octant pairs tested in the 3D
+ * link), "pairs_nn" (query-member pairs evaluated by the large-node
+ * nearest-neighbour searches, refinements included) and "pairs_link" (pairs
+ * of a query and a later member evaluated by the large-node link), launches
+ * counted, no time.  Counting runs slower kernel builds and synchronises
+ * after each counted launch: for measurement runs, not timed ones.
  * rs_profile_get synchronises on the recorded events; unknown names report
  * zeros.  Returns RS_OK, or RS_EINVAL for NULL arguments.
  */

@@ -368,9 +368,11 @@ def rs_seed_assign(x, y, z, vx, vy, vz, box, tree, props, out=None, stream=None)
     return out
 
 
-def rs_profile_enable(on: bool = True) -> None:
-    """Record HIP events around the library's main kernels (instrumentation)."""
-    load().rs_profile_enable(1 if on else 0)
+def rs_profile_enable(on=True) -> None:
+    """Record HIP events around the library's main kernels (instrumentation);
+    on=2 also counts the searches' pair tests ("pairs_fof3d", "pairs_nn",
+    "pairs_link"), with slower counting kernels."""
+    load().rs_profile_enable(2 if on == 2 else (1 if on else 0))
 
 
 def rs_profile_get(name: str):

@@ -228,6 +228,11 @@ inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
 // `units` counts the work items a launch processed (members, particles).
 void prof_begin(const char* name, hipStream_t st);
 void prof_end(const char* name, hipStream_t st, double units);
+// Level 2 of the instrumentation also counts the pair tests of the searches
+// (kernels built with counters, slower; for measurement runs only).  After a
+// counted launch the caller adds its count with prof_add_count (synchronous).
+bool prof_count_pairs();
+void prof_add_count(const char* name, double count);
 
 // Tuning table: launch shapes chosen per size bucket by the autotuner.  Every
 // value is one of a small compiled set; results are the same for all of them.

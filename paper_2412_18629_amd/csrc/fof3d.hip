@@ -209,9 +209,12 @@ RS_DEV float link_d2(float xi, float yi, float zi, float xj, float yj, float zj,
 // bound by them).
 constexpr int LINK_BATCH = 4;
 
-template <bool AUTOLINK, bool PER>
+// member-pair tests of the counting build (instrumentation level 2)
+__device__ unsigned long long g_3d_pairs[64];
+
+template <bool AUTOLINK, bool PER, bool CNT>
 RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int oa, int32_t c,
-                      int dx, int dy, int dz, int32_t& ra) {
+                      int dx, int dy, int dz, int32_t& ra, unsigned long long& npairs) {
     const Grid3& g = A.g;
     const int32_t b0 = A.cell_oct[c], b1 = A.cell_oct[c + 1];
     // an octant pair is skipped when the filter puts it beyond reach
@@ -225,6 +228,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
         for (int32_t b = b0 < a + 1 ? a + 1 : b0; b < b1; b++) {
             if (g.octfilter && far(A.oct_bits[b])) continue;
             const int32_t t0 = A.oct_start[b], t1 = A.oct_start[b + 1];
+            if (CNT) npairs += (unsigned long long)(s1 - s0) * (unsigned long long)(t1 - t0);
             for (int32_t i = s0; i < s1; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
                 for (int32_t j = t0; j < t1; j++)
@@ -270,6 +274,7 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
             for (int32_t i = s0; i < s1 && !hit; i++) {
                 const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
                 for (int32_t j = t0; j < t1; j++) {
+                    if (CNT) npairs++;
                     if (link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j], A.sz[j], g) <= g.ll2) {
                         hit = true;
                         break;
@@ -288,10 +293,11 @@ RS_DEV void link_cell(const LinkArgs& A, int32_t a, int32_t s0, int32_t s1, int 
 // 27-cell neighbourhood.  Octants are numbered in cell-key order, so cells
 // with a smaller key (among them every cell of an earlier row) hold only
 // earlier octants, whose pairs with this one are taken from their side.
-template <bool AUTOLINK, bool PER>
+template <bool AUTOLINK, bool PER, bool CNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_link(LinkArgs A) {
     const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= A.n_oct) return;
+    unsigned long long npairs = 0;   // counting build only
     const Grid3& g = A.g;
     const int32_t s0 = A.oct_start[a], s1 = A.oct_start[a + 1];
     const uint64_t cell = A.keys[s0] >> 3;
@@ -303,6 +309,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const int64_t cz = (int64_t)(row / (uint64_t)nc);
 
     if (!AUTOLINK) {
+        if (CNT) npairs += (unsigned long long)(s1 - s0) * (unsigned long long)(s1 - s0 - 1) / 2;
         for (int32_t i = s0; i < s1; i++) {
             const float xi = A.sx[i], yi = A.sy[i], zi = A.sz[i];
             for (int32_t j = i + 1; j < s1; j++)
@@ -333,8 +340,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                     const uint64_t nkey = A.cell_key[c];
                     if (nkey > khi) break;
                     if (nkey < cell) continue;
-                    link_cell<AUTOLINK, PER>(A, a, s0, s1, oa, c, (int)(nkey - klo) - 1, dy,
-                                             dz, ra);
+                    link_cell<AUTOLINK, PER, CNT>(A, a, s0, s1, oa, c, (int)(nkey - klo) - 1,
+                                                  dy, dz, ra, npairs);
                 }
             } else {
                 for (int dx = -1; dx <= 1; dx++) {
@@ -345,25 +352,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
                     if (nkey < cell) continue;
                     const int32_t c = lower_bound_u64(A.cell_key, rb, re, nkey);
                     if (c < re && A.cell_key[c] == nkey)
-                        link_cell<AUTOLINK, PER>(A, a, s0, s1, oa, c, dx, dy, dz, ra);
+                        link_cell<AUTOLINK, PER, CNT>(A, a, s0, s1, oa, c, dx, dy, dz, ra,
+                                                      npairs);
                 }
             }
         }
     }
+    if (CNT && npairs) atomicAdd(&g_3d_pairs[threadIdx.x & 63], npairs);
 }
 
 
-// slot parents from the flattened octant roots: each slot points at the
-// first slot of its component's root octant (one slot per component is its
-// own parent, as with the slot-level union-find)
 // the deferred octant pairs, one wavefront per pair (grid-stride): skipped
 // when already in one component, otherwise the member pairs are tested 64
 // at a time until the first one within ll
 constexpr int HEAVY_BLOCKS = 8192;
 
-template <bool PER>
+template <bool PER, bool CNT>
 __global__ void __launch_bounds__(64) k_link_heavy(LinkArgs A) {
     const int lane = threadIdx.x;
+    unsigned long long npairs = 0;   // counting build only
     const int32_t nq = min(*A.n_heavy, A.cap_heavy);
     const Grid3& g = A.g;
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
@@ -379,13 +386,18 @@ __global__ void __launch_bounds__(64) k_link_heavy(LinkArgs A) {
                 const int32_t j = j0 + lane;
                 const bool near = j < t1 && link_d2<PER>(xi, yi, zi, A.sx[j], A.sy[j],
                                                          A.sz[j], g) <= g.ll2;
+                if (CNT) npairs += (unsigned long long)min(64, t1 - j0);
                 hit = __ballot(near) != 0;
             }
         }
         if (hit && lane == 0) uf_unite(A.parent, ra, rb);
     }
+    if (CNT && lane == 0 && npairs) atomicAdd(&g_3d_pairs[blockIdx.x & 63], npairs);
 }
 
+// slot parents from the flattened octant roots: each slot points at the
+// first slot of its component's root octant (one slot per component is its
+// own parent, as with the slot-level union-find)
 __global__ void k_oct2slot(int64_t n, const int32_t* __restrict__ oflag,
                            const int32_t* __restrict__ oex, const int32_t* __restrict__ oct_start,
                            const int32_t* __restrict__ poct, int32_t* __restrict__ parent) {
@@ -507,16 +519,33 @@ size_t fof3d_bytes(int64_t n, const Grid3& g) {
     return bytes;
 }
 
-template <bool PER>
-static int link_pass(const LinkArgs& A, unsigned go, hipStream_t st) {
+template <bool PER, bool CNT>
+static int link_launch(const LinkArgs& A, unsigned go, hipStream_t st) {
     if (A.g.autolink) {
         RS_TRY(fill_i32(A.n_heavy, 0, 1, st));
-        k_link<true, PER><<<go, 256, 0, st>>>(A);
-        k_link_heavy<PER><<<HEAVY_BLOCKS, 64, 0, st>>>(A);
+        k_link<true, PER, CNT><<<go, 256, 0, st>>>(A);
+        k_link_heavy<PER, CNT><<<HEAVY_BLOCKS, 64, 0, st>>>(A);
     } else {
-        k_link<false, PER><<<go, 256, 0, st>>>(A);
+        k_link<false, PER, CNT><<<go, 256, 0, st>>>(A);
     }
     RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+template <bool PER>
+static int link_pass(const LinkArgs& A, unsigned go, hipStream_t st) {
+    if (!prof_count_pairs()) return link_launch<PER, false>(A, go, st);
+    // counting build: counters cleared before, read back after (synchronous)
+    unsigned long long h[64] = {0};
+    RS_HIP(hipStreamSynchronize(st));
+    RS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_3d_pairs), h, sizeof(h)));
+    RS_TRY((link_launch<PER, true>(A, go, st)));
+    RS_HIP(hipMemcpyFromSymbolAsync(h, HIP_SYMBOL(g_3d_pairs), sizeof(h), 0,
+                                    hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (int i = 0; i < 64; i++) sum += (double)h[i];
+    prof_add_count("pairs_fof3d", sum);
     return RS_OK;
 }
 

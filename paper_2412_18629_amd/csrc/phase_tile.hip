@@ -87,7 +87,10 @@ RS_DEV float bcast(float v, int src) {
 // within l are queued in LDS and united 64 at a time, one pair per lane, so
 // that the union-find walks of many pairs are in flight together instead of
 // one or two lanes walking while the rest of the wavefront waits.
-template <bool O32>
+// pair tests of the counting build (instrumentation level 2)
+__device__ unsigned long long g_link_pairs[64];
+
+template <bool O32, bool CNT>
 __global__ void __launch_bounds__(64)
 k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
             int32_t* __restrict__ par) {
@@ -130,6 +133,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
     const int64_t first_act = ts + __ffsll((unsigned long long)amask) - 1;
 
     int nhit = 0;
+    unsigned long long npairs = 0;   // counting build only
     auto unite_hits = [&]() {
         __syncthreads();
         for (int i = lane; i < nhit; i += 64) uf_unite(par, hits[i].x, hits[i].y);
@@ -169,6 +173,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
                                                    wj, P.a, P.c, pp.L, pp.h);
                 const int32_t k0 = off + src;
                 const uint64_t later = k0 <= 0 ? hasm : (k0 >= 64 ? 0ull : hasm & (~0ull << k0));
+                if (CNT) npairs += (unsigned long long)__popcll(later);
                 const uint64_t hm = later & __builtin_amdgcn_ballot_w64(dd <= l2);
                 if (hm) {
                     if (nhit + __popcll(hm) > THITS) unite_hits();
@@ -247,16 +252,33 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
     if (P.nowrap) process(nlist, std::true_type{});
     else process(nlist, std::false_type{});
     unite_hits();
+    if (CNT && lane == 0 && npairs) atomicAdd(&g_link_pairs[blockIdx.x & 63], npairs);
 }
 
 int tile_link(const TArgs& A, int ntiles, const float* d2, int32_t* par, hipStream_t st) {
     if (ntiles <= 0) return RS_OK;
     const int c = xcd_chunk(ntiles);
-    if (use_o32(A.nmem))
-        k_tile_link<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);
-    else
-        k_tile_link<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2, par);
+    const bool o32 = use_o32(A.nmem);
+    const unsigned grid = xcd_chunk_grid(ntiles, c);
+    if (!prof_count_pairs()) {
+        if (o32) k_tile_link<true, false><<<grid, 64, 0, st>>>(A, ntiles, c, d2, par);
+        else k_tile_link<false, false><<<grid, 64, 0, st>>>(A, ntiles, c, d2, par);
+        RS_HIP(hipGetLastError());
+        return RS_OK;
+    }
+    // counting build: counters cleared before, read back after (synchronous)
+    unsigned long long h[64] = {0};
+    RS_HIP(hipStreamSynchronize(st));
+    RS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_link_pairs), h, sizeof(h)));
+    if (o32) k_tile_link<true, true><<<grid, 64, 0, st>>>(A, ntiles, c, d2, par);
+    else k_tile_link<false, true><<<grid, 64, 0, st>>>(A, ntiles, c, d2, par);
     RS_HIP(hipGetLastError());
+    RS_HIP(hipMemcpyFromSymbolAsync(h, HIP_SYMBOL(g_link_pairs), sizeof(h), 0,
+                                    hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (int i = 0; i < 64; i++) sum += (double)h[i];
+    prof_add_count("pairs_link", sum);
     return RS_OK;
 }
 

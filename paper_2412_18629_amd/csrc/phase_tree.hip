@@ -381,7 +381,11 @@ RS_DEV StackEnt stack_unpack(StackSlot s) {
 // depth-first descent from the node's root.  One wavefront per tile of
 // queries, one query at a time; child records are bounded lane-parallel,
 // surviving leaves are scanned four at a time with independent loads.
-template <bool O32>
+// pair tests of the counting build (instrumentation level 2), spread over 64
+// counters to keep the atomics apart
+__device__ unsigned long long g_nn_pairs[64];
+
+template <bool O32, bool CNT>
 __global__ void __launch_bounds__(64)
 k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
     __shared__ StackSlot stk[STACK_PER_WAVE];
@@ -425,6 +429,7 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
     const float redo = mode == 3 || mode == 6 ? 0.0f : __builtin_huge_valf();
     const bool refine = mode >= 3;
     const int32_t rf = tb.cfirst[A.root[v]], rn = tb.ccount[A.root[v]];
+    unsigned long long npairs = 0;   // counting build only
     for (int64_t qm = ts; qm < te; qm++) {
         if (refine && !(d2out[qm] == redo)) continue;
         const TQuery q = tq_load(T, qm, P, A.pp);
@@ -436,6 +441,7 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
             if (m < r0[13] && m != qm) bl = fminf(bl, tq_d2<O32>(T, m, q, P, A.pp));
         }
         float best = wmin_nonneg(bl);
+        if (CNT) npairs += (unsigned long long)(r0[13] - r0[12] - 1);
         // a node's root is never a finest cell: at most 64 children
         if (lane == 0) stk[0] = stack_pack(0, rf, rn, 0.0f);
         int sp = best <= lo2 ? 0 : 1;
@@ -526,6 +532,8 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                             cnt++;
                         }
                     }
+                    if (CNT)
+                        for (int j = 0; j < cnt; j++) npairs += (unsigned long long)(e4[j] - s4[j]);
                     float mx[4], my[4], mz[4], mu[4], mv[4], mw[4];
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
@@ -572,6 +580,7 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
             d2out[qm] = out;
         }
     }
+    if (CNT && lane == 0 && npairs) atomicAdd(&g_nn_pairs[blockIdx.x & 63], npairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -661,11 +670,26 @@ int tree_refit_active(TreeBuf& tb, int32_t n_entry, const std::vector<int32_t>& 
 
 int tree_nn(const TArgs& A, int ntiles, float* d2, hipStream_t st) {
     const int c = xcd_chunk(ntiles);
-    if (use_o32(A.nmem))
-        k_tree_nn<true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
-    else
-        k_tree_nn<false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
+    const bool o32 = use_o32(A.nmem);
+    if (!prof_count_pairs()) {
+        if (o32) k_tree_nn<true, false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
+        else k_tree_nn<false, false><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
+        RS_HIP(hipGetLastError());
+        return RS_OK;
+    }
+    // counting build: counters cleared before, read back after (synchronous)
+    unsigned long long h[64] = {0};
+    RS_HIP(hipStreamSynchronize(st));
+    RS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_nn_pairs), h, sizeof(h)));
+    if (o32) k_tree_nn<true, true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
+    else k_tree_nn<false, true><<<xcd_chunk_grid(ntiles, c), 64, 0, st>>>(A, ntiles, c, d2);
     RS_HIP(hipGetLastError());
+    RS_HIP(hipMemcpyFromSymbolAsync(h, HIP_SYMBOL(g_nn_pairs), sizeof(h), 0,
+                                    hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (int i = 0; i < 64; i++) sum += (double)h[i];
+    prof_add_count("pairs_nn", sum);
     return RS_OK;
 }
 

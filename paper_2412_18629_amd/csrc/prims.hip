@@ -182,6 +182,7 @@ struct ProfRec {
 };
 
 static bool g_prof_on = false;
+static bool g_prof_pairs = false;
 static std::map<std::string, ProfRec> g_prof;
 static std::map<std::string, hipEvent_t> g_prof_open;
 static std::mutex g_prof_mu;
@@ -208,6 +209,15 @@ void prof_end(const char* name, hipStream_t st, double units) {
     r.stop.push_back(e);
     r.units.push_back(units);
     g_prof_open.erase(it);
+}
+
+bool prof_count_pairs() { return g_prof_on && g_prof_pairs; }
+
+void prof_add_count(const char* name, double count) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    ProfRec& r = g_prof[name];
+    r.done_launches++;
+    r.done_units += count;
 }
 
 static void prof_drain(ProfRec& r) {
@@ -383,6 +393,7 @@ int rs_profile_enable(int on) {
         rs::g_prof.clear();
     }
     rs::g_prof_on = on != 0;
+    rs::g_prof_pairs = on == 2;
     return RS_OK;
 }
 

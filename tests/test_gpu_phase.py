@@ -253,3 +253,24 @@ def test_shared_workspace_alternating_calls():
     ref_lab = oracle.fof3d(*sm[:3], small.box, small.link_len)
     assert np.array_equal(labs.cpu().numpy(), ref_lab)
     compare(trees, oracle.phase_fof(*sm, small.box, ref_lab))
+
+
+def test_pair_counting_leaves_results_unchanged():
+    # instrumentation level 2 runs counting builds of the searches: the same
+    # labels and tree, and positive pair-test counts for each search
+    cfg = synth.scaled(synth.CONFIGS["c32"], 300000)
+    d = [a.cuda() for a in synth.generate(cfg, 5)]
+    lab, _ = rs.rs_fof3d(d[0], d[1], d[2], cfg.box, cfg.link_len)
+    ref = rs.rs_phase_fof_batch(*d, cfg.box, lab, flags=rs.RS_BATCHED)
+    try:
+        rs.rs_profile_enable(2)
+        lab2, _ = rs.rs_fof3d(d[0], d[1], d[2], cfg.box, cfg.link_len)
+        got = rs.rs_phase_fof_batch(*d, cfg.box, lab2, flags=rs.RS_BATCHED)
+        counts = {k: rs.rs_profile_get(k) for k in ("pairs_fof3d", "pairs_nn", "pairs_link")}
+    finally:
+        rs.rs_profile_enable(False)
+    assert torch.equal(lab, lab2)
+    for k in ("level", "min_index", "parent", "size", "l2", "a", "c", "deepest"):
+        assert torch.equal(ref[k], got[k]), k
+    for k, (ms, launches, pairs) in counts.items():
+        assert launches >= 1 and pairs > 0, (k, launches, pairs)
