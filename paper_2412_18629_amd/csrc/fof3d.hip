@@ -203,11 +203,11 @@ RS_DEV float link_d2(float xi, float yi, float zi, float xj, float yj, float zj,
 // after each union (a stale one only costs a redundant test).  With
 // auto-link the union-find runs over octant indices (one element per octant,
 // a dense array half the size of the slot array); otherwise over slots.
-// The auto-linked pass takes the cell's octants in batches: their octant
-// bits and union-find parents are loaded together, so that the latencies
-// overlap instead of adding up along the thread's serial walk (the walk is
-// bound by them).
-constexpr int LINK_BATCH = 4;
+// The auto-linked pass takes the cell's octants in pairs: their octant bits
+// and union-find parents are loaded together, so that the latencies overlap
+// instead of adding up along the thread's serial walk (the walk is bound by
+// them; larger batches spill registers).
+constexpr int LINK_BATCH = 2;
 
 // member-pair tests of the counting build (instrumentation level 2)
 __device__ unsigned long long g_3d_pairs[64];
