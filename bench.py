@@ -63,9 +63,12 @@ FLAGS = {"learned": rs.RS_LEARNED, "batched": rs.RS_BATCHED, "plain": rs.RS_PLAI
 # device symbol and source files of each instrumented kernel (the PMC summary
 # is only used while these sources are unchanged)
 KERNEL_SYMBOL = {
-    "fof3d_link": ("void rs::k_link<", ["fof3d.hip", "common.h"]),
-    "phase_large_nn": ("void rs::k_tree_nn<", ["phase_tree.hip", "phase_common.h", "common.h"]),
-    "phase_large_link": ("void rs::k_tile_link<", ["phase_tile.hip", "phase_common.h", "common.h"]),
+    # the timed instantiations (32-bit member offsets, no pair counters)
+    "fof3d_link": ("void rs::k_link<true, true, false>(", ["fof3d.hip", "common.h"]),
+    "phase_large_nn": ("void rs::k_tree_nn<true, false>(",
+                       ["phase_tree.hip", "phase_common.h", "common.h"]),
+    "phase_large_link": ("void rs::k_tile_link<true, false>(",
+                         ["phase_tile.hip", "phase_common.h", "common.h"]),
     "phase_small": ("void rs::k_small_subtree<",
                     ["phase_small.hip", "phase_common.h", "common.h"]),
     "halo_props": ("rs::k_pr_large(", ["props.hip", "common.h"]),
@@ -414,6 +417,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the halo-property, seed-assignment and sub-box timings")
+    ap.add_argument("--no-pairs", action="store_true",
+                    help="skip the extra step that counts pair tests")
     ap.add_argument("--no-subbox", action="store_true",
                     help="skip the sub-box timing (its 3D link launches would mix with the "
                          "step's in a profile)")
@@ -507,9 +512,10 @@ def main():
     }
     progress(f"{args.steps} steps at {ms:.1f} ms")
     line["small_node_kernels"] = small_node_stats(tree, prof_small, args.steps)
-    line["pair_tests"] = pair_tests(arrs, cfg, args.form, labels, model,
-                                    line["config"]["kernel_ms_per_step"])
-    progress("pair tests counted")
+    if not args.no_pairs:
+        line["pair_tests"] = pair_tests(arrs, cfg, args.form, labels, model,
+                                        line["config"]["kernel_ms_per_step"])
+        progress("pair tests counted")
     if not args.no_rows:
         line["hierarchy_rows"] = hierarchy_rows(arrs, cfg, tree, subbox=not args.no_subbox)
         progress("halo properties and seed assignment timed")
