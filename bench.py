@@ -284,10 +284,11 @@ def seed_tests(tree):
     return int((own[has] * leafcnt[has]).sum().item())
 
 
-def subbox_row(arrs, cfg, reps=3):
-    """rs_fof3d_subbox on one process's share of an 8-way decomposition: the
-    cube [gw, gw + L/2)^3 with its ghost shell of width gw = 1.5 ll, selected
-    on the device with the sub-box's own fp32 bounds."""
+def subbox_cut(arrs, cfg):
+    """One process's share of an 8-way decomposition of the workload: the
+    cube [gw, gw + L/2)^3 and its ghost shell of width gw = 1.5 ll, selected
+    on the device with the sub-box's own fp32 bounds (owned particles first).
+    Returns (x, y, z, n_owned, lo, hi, gw)."""
     gw = 1.5 * cfg.link_len
     side = cfg.box / 2.0
     lo32 = torch.full((3,), gw, dtype=torch.float32)
@@ -304,7 +305,14 @@ def subbox_row(arrs, cfg, reps=3):
     idx = torch.cat([torch.nonzero(owned).squeeze(1), torch.nonzero(shell & ~owned).squeeze(1)])
     sx, sy, sz = (c[idx].contiguous() for c in (x, y, z))
     n_owned = int(owned.sum().item())
-    del owned, shell, idx
+    return sx, sy, sz, n_owned, lo32.tolist(), hi32.tolist(), gw
+
+
+def subbox_row(arrs, cfg, reps=3):
+    """rs_fof3d_subbox on one process's share of an 8-way decomposition
+    (subbox_cut), timed."""
+    sx, sy, sz, n_owned, lo, hi, gw = subbox_cut(arrs, cfg)
+    lo32, hi32 = torch.tensor(lo), torch.tensor(hi)
     labels = torch.empty(sx.numel(), dtype=torch.int32, device=sx.device)
     call = lambda: rs.rs_fof3d_subbox(sx, sy, sz, n_owned, lo32.tolist(), hi32.tolist(), gw,
                                       cfg.link_len, labels=labels)

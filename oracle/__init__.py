@@ -58,6 +58,7 @@ def _load():
     lib.oracle_halo_props.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P]
     lib.oracle_seed_assign.argtypes = [P, P, P, P, P, P, i64, f32, i64, P, P, P, P, P, P]
     lib.oracle_fof3d_subbox.argtypes = [P, P, P, i64, i64, P, P, f32, f32, ctypes.c_int, P]
+    lib.oracle_fof3d_subbox_mode.argtypes = [P, P, P, i64, i64, P, P, f32, f32, ctypes.c_int, P]
     _lib = lib
     return lib
 
@@ -91,20 +92,24 @@ def fof3d(x, y, z, box, link_len, brute=False, grid="auto"):
     return lab
 
 
-def fof3d_subbox(x, y, z, n_owned, lo, hi, ghost_width, link_len, brute=False):
+def fof3d_subbox(x, y, z, n_owned, lo, hi, ghost_width, link_len, brute=False, grid="auto"):
     """3D FoF over a non-periodic sub-box [lo, hi) whose particles [0, n_owned)
     are owned and the rest are ghosts within ghost_width of it.  Returns
     (labels, ghost_links): labels = smallest member index per group; the
     ghost links are the (ghost index, label) pairs of the ghosts whose group
-    holds an owned particle (label < n_owned), by ghost index."""
+    holds an owned particle (label < n_owned), by ghost index.  grid: "auto"
+    (small cells with same-cell linking where the sub-box allows it) or
+    "coarse" (cells of side >= the margin, every member pair tested);
+    brute=True tests all pairs."""
     lib = _load()
     x, y, z = _f32(x), _f32(y), _f32(z)
     n = x.size
     lab = np.empty(n, dtype=np.int32)
     lo3, hi3 = _f32(lo), _f32(hi)
-    rc = lib.oracle_fof3d_subbox(_ptr(x), _ptr(y), _ptr(z), n, int(n_owned), _ptr(lo3),
-                                 _ptr(hi3), float(ghost_width), float(link_len),
-                                 1 if brute else 0, _ptr(lab))
+    mode = 1 if brute else {"auto": 0, "coarse": 2}[grid]
+    rc = lib.oracle_fof3d_subbox_mode(_ptr(x), _ptr(y), _ptr(z), n, int(n_owned), _ptr(lo3),
+                                      _ptr(hi3), float(ghost_width), float(link_len), mode,
+                                      _ptr(lab))
     if rc != 0:
         raise OracleError(f"oracle_fof3d_subbox failed: {rc}")
     g = np.arange(int(n_owned), n, dtype=np.int32)

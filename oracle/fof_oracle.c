@@ -397,18 +397,108 @@ static float pos_d2_open(const float *x, const float *y, const float *z, int64_t
     return t + sz;
 }
 
-int oracle_fof3d_subbox(const float *x, const float *y, const float *z, int64_t n,
-                        int64_t n_owned, const float *lo, const float *hi, float gw, float ll,
-                        int brute, int32_t *labels)
+/*
+ * The small-cell grid of the sub-box (no periodic images): cells of side
+ * E / nc <= ll / sqrt(3 (1 + 1e-5)) over [o, o + E)^3, so that every pair in
+ * one cell is within ll by any rounding and the cell's members are united
+ * without tests; cell pairs up to r cells apart on every axis (the margin of
+ * the coarse grid in cell units) are joined at their first linked member
+ * pair, pairs already in one component skipped.  The same closure as
+ * testing every pair.
+ */
+static int fof3d_fine_open(const float *x, const float *y, const float *z, int64_t n,
+                           const double *o, double E, float ll, int64_t nc, int64_t r,
+                           int32_t *labels)
+{
+    float ll2 = ll * ll;
+    double scale = (double)nc / E;
+    const float *pc[3] = { x, y, z };
+    kv_t *s = (kv_t *)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *rowstart = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc * nc + 1));
+    if (!s || !parent || !rowstart) { free(s); free(parent); free(rowstart); return -3; }
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c[3];
+        for (int a = 0; a < 3; a++) {
+            c[a] = (int64_t)floor(((double)pc[a][i] - o[a]) * scale);
+            if (c[a] >= nc) c[a] = nc - 1;
+            if (c[a] < 0) c[a] = 0;
+        }
+        s[i].key = (c[2] * nc + c[1]) * nc + c[0];
+        s[i].idx = i;
+        parent[i] = i;
+    }
+    qsort(s, (size_t)n, sizeof(kv_t), cmp_kv);
+    int64_t ncell = 0;
+    for (int64_t p = 0; p < n; p++)
+        if (p == 0 || s[p].key != s[p - 1].key) ncell++;
+    int64_t *cfirst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell + 1));
+    int64_t *ckey = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    if (!cfirst || !ckey) {
+        free(s); free(parent); free(rowstart); free(cfirst); free(ckey);
+        return -3;
+    }
+    int64_t k = 0;
+    for (int64_t p = 0; p < n; p++) {
+        if (p == 0 || s[p].key != s[p - 1].key) {
+            cfirst[k] = p;
+            ckey[k] = s[p].key;
+            k++;
+        } else {
+            uf_union(parent, s[cfirst[k - 1]].idx, s[p].idx);
+        }
+    }
+    cfirst[ncell] = n;
+    for (int64_t R = 0, c = 0; R <= nc * nc; R++) {
+        while (c < ncell && ckey[c] < R * nc) c++;
+        rowstart[R] = c;
+    }
+    for (int64_t a = 0; a < ncell; a++) {
+        int64_t key = ckey[a];
+        int64_t cx = key % nc, cy = (key / nc) % nc, cz = key / (nc * nc);
+        int64_t pa = s[cfirst[a]].idx;
+        for (int64_t dz = -r; dz <= r; dz++)
+        for (int64_t dy = -r; dy <= r; dy++) {
+            int64_t oy = cy + dy, oz = cz + dz;
+            if (oy < 0 || oz < 0 || oy >= nc || oz >= nc) continue;
+            int64_t R = oz * nc + oy;
+            for (int64_t b = rowstart[R]; b < rowstart[R + 1]; b++) {
+                if (ckey[b] <= key) continue;               /* each cell pair once */
+                int64_t dxc = (ckey[b] - R * nc) - cx;
+                if (dxc < -r || dxc > r) continue;
+                int64_t pb = s[cfirst[b]].idx;
+                if (uf_find(parent, pa) == uf_find(parent, pb)) continue;
+                int found = 0;
+                for (int64_t p = cfirst[a]; p < cfirst[a + 1] && !found; p++)
+                    for (int64_t q = cfirst[b]; q < cfirst[b + 1]; q++)
+                        if (pos_d2_open(x, y, z, s[p].idx, s[q].idx) <= ll2) {
+                            found = 1;
+                            break;
+                        }
+                if (found) uf_union(parent, pa, pb);
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
+    free(s); free(parent); free(rowstart); free(cfirst); free(ckey);
+    return 0;
+}
+
+/*
+ * 3D FoF of a sub-box.  mode 0: the small-cell grid where it allows (at
+ * least 2r + 1 cells per axis, a row table of at most 2^26 rows), else the
+ * coarse grid; 1: all pairs; 2: the coarse grid (cells of side >= the
+ * margin, every member pair of neighbouring cells tested).
+ */
+int oracle_fof3d_subbox_mode(const float *x, const float *y, const float *z, int64_t n,
+                             int64_t n_owned, const float *lo, const float *hi, float gw,
+                             float ll, int mode, int32_t *labels)
 {
     if (n < 0 || n_owned < 0 || n_owned > n || !(ll > 0.0f) || !(gw >= 0.0f)) return -1;
     for (int a = 0; a < 3; a++)
         if (!(hi[a] > lo[a])) return -1;
     if (check_subbox(x, y, z, n, n_owned, lo, hi, gw)) return -2;
     float ll2 = ll * ll;
-    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    if (!parent) return -3;
-    for (int64_t i = 0; i < n; i++) parent[i] = i;
     double o[3], E = 0.0;
     for (int a = 0; a < 3; a++) {
         o[a] = (double)lo[a] - (double)gw;
@@ -416,8 +506,21 @@ int oracle_fof3d_subbox(const float *x, const float *y, const float *z, int64_t 
         if (e > E) E = e;
     }
     double side_min = (double)ll * (1.0 + ldexp(1.0, -20)) + E * ldexp(1.0, -22);
+    if (mode == 0) {
+        double smax = (double)ll / sqrt(3.0 * (1.0 + 1e-5));
+        double cnt = ceil(E / smax);
+        if (cnt <= 1048576.0) {
+            int64_t ncf = (int64_t)cnt;
+            int64_t r = (int64_t)floor(side_min / (E / (double)ncf)) + 1;
+            if (ncf >= 2 * r + 1 && ncf * ncf <= ((int64_t)1 << 26))
+                return fof3d_fine_open(x, y, z, n, o, E, ll, ncf, r, labels);
+        }
+    }
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!parent) return -3;
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
     int64_t nc = (int64_t)floor(E / side_min);
-    if (brute || nc < 3 || nc > 2000000) {
+    if (mode == 1 || nc < 3 || nc > 2000000) {
         for (int64_t i = 0; i < n; i++)
             for (int64_t j = i + 1; j < n; j++)
                 if (pos_d2_open(x, y, z, i, j) <= ll2) uf_union(parent, i, j);
@@ -464,6 +567,14 @@ int oracle_fof3d_subbox(const float *x, const float *y, const float *z, int64_t 
     for (int64_t i = 0; i < n; i++) labels[i] = (int32_t)uf_find(parent, i);
     free(parent);
     return 0;
+}
+
+int oracle_fof3d_subbox(const float *x, const float *y, const float *z, int64_t n,
+                        int64_t n_owned, const float *lo, const float *hi, float gw, float ll,
+                        int brute, int32_t *labels)
+{
+    return oracle_fof3d_subbox_mode(x, y, z, n, n_owned, lo, hi, gw, ll, brute ? 1 : 0,
+                                    labels);
 }
 
 /* ------------------------------------------------------------------ */

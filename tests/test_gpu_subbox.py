@@ -106,3 +106,28 @@ def test_errors_leave_outputs_untouched():
     assert e.value.status == rs.RS_EINVAL
     lab2, links = rs.rs_fof3d_subbox(*t, 1, lo, hi, 0.5, 0.2)
     assert lab2.cpu().tolist() == [0, 1] and links.shape == (0, 2)
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_bench_cut():
+    # the sub-box the benchmark times: one eighth of the 512^3 workload (the
+    # cube [1.5 ll, 1.5 ll + L/2)^3, 15.5M owned particles and its 1.5 ll
+    # ghost shell), every label and ghost link against the oracle
+    import bench
+    cfg = synth.CONFIGS["c512"]
+    arrs = synth.generate(cfg, 0, device=torch.device("cuda"))
+    sx, sy, sz, no, lo, hi, gw = bench.subbox_cut(arrs, cfg)
+    del arrs
+    lab, links = rs.rs_fof3d_subbox(sx, sy, sz, no, lo, hi, gw, cfg.link_len)
+    torch.cuda.synchronize()
+    got, gl = lab.cpu().numpy(), links.cpu().numpy()
+    h = [t.cpu().numpy() for t in (sx, sy, sz)]
+    del sx, sy, sz, lab, links
+    torch.cuda.empty_cache()
+    print(f"sub-box of {h[0].size} particles ({no} owned): oracle running", flush=True)
+    ref, rl = oracle.fof3d_subbox(*h, no, lo, hi, gw, cfg.link_len)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gl, rl)
+    assert rl.shape[0] > 0
+    print(f"sub-box: all {ref.size} labels and {rl.shape[0]} ghost links equal the oracle's",
+          flush=True)

@@ -101,3 +101,51 @@ def _decomposition(parts, n=12000, seed=0):
 def test_decomposition_reproduces_the_periodic_box(parts):
     whole, joined = _decomposition(parts)
     assert np.array_equal(joined, whole)
+
+
+@pytest.mark.parametrize("seed,clustered", [(4, False), (5, True), (6, True)])
+def test_small_cell_grid_matches_coarse_and_brute(seed, clustered):
+    # the small-cell grid of the sub-box against the coarse grid and all
+    # pairs, on sub-boxes with dense clumps (same-cell linking) and faces
+    pos, no, lo, hi, gw = _random_subbox(seed, n_own=6000, n_ghost=1500, clustered=clustered)
+    ll = F32(0.17)
+    x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+    ref = brute.fof3d(x, y, z, None, ll)
+    for grid in ("auto", "coarse"):
+        lab, _ = oracle.fof3d_subbox(x, y, z, no, lo, hi, gw, ll, grid=grid)
+        assert np.array_equal(lab, ref), grid
+
+
+@pytest.mark.parametrize("ll", [0.2, 0.175, 0.5])
+def test_small_cell_linking_stays_inside_ll(ll):
+    # pairs along the diagonal of the cells of every grid the sub-box could
+    # plausibly use (around E sqrt(3) / ll cells of side E / nc from the
+    # shell's corner), separated by between 0.995 ll and the cell's diagonal
+    # (or 1.005 ll), all owned: same-cell linking may only join pairs the pair
+    # test joins (a cell whose diagonal exceeds ll would link pairs farther
+    # apart than ll)
+    ll = F32(ll)
+    lo = np.array([1.0, 1.0, 1.0], F32)
+    hi = np.array([9.0, 9.0, 9.0], F32)
+    gw = F32(0.5)
+    o = lo.astype(np.float64) - float(gw)
+    E = float(hi[0]) + float(gw) - o[0]
+    rng = np.random.default_rng(int(float(ll) * 1000))
+    pts = []
+    n0 = int(round(E * np.sqrt(3.0) / float(ll)))
+    for nc in range(n0 - 2, n0 + 3):
+        side = E / nc
+        k = int(np.ceil((float(gw) + 1.0) / side))   # cells kept clear of the shell
+        top = max(side * np.sqrt(3.0) / float(ll), 1.005)
+        for f in np.linspace(0.995, top, 24):
+            c = rng.integers(k, nc - k, 3)
+            p = o + c * side + 2e-6 * side
+            pts += [p, p + float(ll) * f / np.sqrt(3.0)]
+    pos = np.array(pts).astype(F32)
+    assert np.all((pos >= lo) & (pos < hi))
+    x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+    ref = brute.fof3d(x, y, z, None, ll)
+    lab, _ = oracle.fof3d_subbox(x, y, z, pos.shape[0], lo, hi, gw, ll)
+    assert np.array_equal(lab, ref)
+    linked = ref[0::2] == ref[1::2]
+    assert linked.any() and not linked.all()
