@@ -22,7 +22,9 @@ plus properties that hold at any size (tests/fullsize_checks.py):
   * the 6D subtree of every sampled group up to 1.5M members (1M at
     1024^3; the oracle needs minutes per larger group, single-threaded):
     the oracle's hierarchy of that member set, field by field, and the halo
-    properties and seeds the oracle computes from it.
+    properties and seeds the oracle computes from it;
+  * at 512^3 and 256^3, the halo properties of every node against the
+    oracle's from the same hierarchy.
 """
 from concurrent.futures import ThreadPoolExecutor
 from concurrent.futures import TimeoutError as FuturesTimeout
@@ -102,6 +104,24 @@ def test_fullsize_parity(config, form, full3d, closure_max, subtree_max):
         # every label of the box equals the oracle's
         assert np.array_equal(R["labels"], R["oracle_labels"])
         print(f"{cfg.name}: all {cfg.n} labels equal the oracle's", flush=True)
+        # the halo properties of every node, against the oracle's from the
+        # same hierarchy (the hierarchy itself is checked below)
+        T = R["tree"]
+        with ThreadPoolExecutor(1) as pool:
+            fut = pool.submit(oracle.halo_props, *R["host"], cfg.box, T["parent"],
+                              T["min_index"], T["deepest"])
+            waited = 0
+            while True:
+                try:
+                    P = fut.result(timeout=30)
+                    break
+                except FuturesTimeout:
+                    waited += 30
+                    print(f"{cfg.name}: oracle halo properties still running ({waited} s)",
+                          flush=True)
+        assert np.array_equal(R["props"].view(np.int32), P.view(np.int32))
+        print(f"{cfg.name}: halo properties of all {P.shape[1]} nodes equal the oracle's",
+              flush=True)
     n3, n6 = check_all(R, cfg, subtree_max=subtree_max, closure_max=closure_max,
                        log=lambda s: print(s, flush=True))
     assert n3 >= 50 and n6 >= 45
