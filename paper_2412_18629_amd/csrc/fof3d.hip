@@ -87,16 +87,28 @@ __global__ void k_keys(const float* __restrict__ x, const float* __restrict__ y,
     idx[i] = (int32_t)i;
 }
 
-__global__ void k_gather3(const int32_t* __restrict__ perm, const float* __restrict__ x,
-                          const float* __restrict__ y, const float* __restrict__ z,
+// positions interleaved, 12 bytes a particle, so that the gather below
+// fetches one record (one or two cache lines) per particle instead of three
+// scattered values
+__global__ void k_interleave3(int64_t n, const float* __restrict__ x,
+                              const float* __restrict__ y, const float* __restrict__ z,
+                              float* __restrict__ rec) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rec[3 * i] = x[i];
+    rec[3 * i + 1] = y[i];
+    rec[3 * i + 2] = z[i];
+}
+
+__global__ void k_gather3(const int32_t* __restrict__ perm, const float* __restrict__ rec,
                           int64_t n, float* __restrict__ sx, float* __restrict__ sy,
                           float* __restrict__ sz) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
-    int32_t i = perm[s];
-    sx[s] = x[i];
-    sy[s] = y[i];
-    sz[s] = z[i];
+    const int64_t i = perm[s];
+    sx[s] = rec[3 * i];
+    sy[s] = rec[3 * i + 1];
+    sz[s] = rec[3 * i + 2];
 }
 
 // run-start flags of octants and of cells in the sorted key order
@@ -503,8 +515,8 @@ size_t fof3d_bytes(int64_t n, const Grid3& g) {
     const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
     size_t bytes = 0;
     auto add = [&](size_t b) { bytes += arena_round(b); };
-    add(8 * n); add(8 * n);                 // keys in / out
-    add(4 * n); add(4 * n);                 // index in / perm
+    add(12 * n);                            // keys and index in; then interleaved positions
+    add(8 * n); add(4 * n);                 // keys out, perm
     add(12 * n);                            // sorted positions
     add(4 * n); add(4 * n); add(4 * n); add(4 * n);   // flags + scans
     add(4 * (n + 1)); add(n + 1);           // octant start, bits
@@ -559,9 +571,13 @@ int fof3d_core(const float* x, const float* y, const float* z, int64_t n, const 
     const uint64_t rows = (uint64_t)g.nc * (uint64_t)g.nc;
     const bool row_table = use_row_table(n, g);
     const int64_t cap_heavy = n / 4 + 1024;
-    uint64_t* kin = take<uint64_t>(ar, n);
+    // the sort's keys and indices in share one region, which holds the
+    // interleaved positions once the sort has consumed them
+    char* kreg = take<char>(ar, 12 * (size_t)n);
+    uint64_t* kin = reinterpret_cast<uint64_t*>(kreg);
+    int32_t* vin = reinterpret_cast<int32_t*>(kreg + 8 * (size_t)n);
+    float* prec = reinterpret_cast<float*>(kreg);
     uint64_t* kout = take<uint64_t>(ar, n);
-    int32_t* vin = take<int32_t>(ar, n);
     int32_t* perm = take<int32_t>(ar, n);
     float* sx = take<float>(ar, n);
     float* sy = take<float>(ar, n);
@@ -591,7 +607,8 @@ int fof3d_core(const float* x, const float* y, const float* z, int64_t n, const 
     k_keys<<<gb, BT, 0, st>>>(x, y, z, n, g, B, kin, vin, cnt + 0);
     RS_HIP(hipGetLastError());
     RS_TRY(sort_pairs_u64_i32(kin, kout, vin, perm, n, g.key_bits, stemp, stb, st));
-    k_gather3<<<gb, BT, 0, st>>>(perm, x, y, z, n, sx, sy, sz);
+    k_interleave3<<<gb, BT, 0, st>>>(n, x, y, z, prec);
+    k_gather3<<<gb, BT, 0, st>>>(perm, prec, n, sx, sy, sz);
     k_run_flags<<<gb, BT, 0, st>>>(kout, n, oflag, cflag);
     RS_HIP(hipGetLastError());
     RS_TRY(scan_exclusive_i32(oflag, oex, n, ctemp, cnt + 1, st));

@@ -76,10 +76,22 @@ __global__ void k_p_keep(int32_t nruns, const int32_t* __restrict__ rstart, int3
     klen[r] = k ? len : 0;
 }
 
+// the six phase-space coordinates of every particle interleaved, 24 bytes a
+// particle, so that the gather below fetches one record (one or two cache
+// lines) per member instead of six scattered values
+__global__ void k_p_interleave(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
+                               const float* __restrict__ z, const float* __restrict__ vx,
+                               const float* __restrict__ vy, const float* __restrict__ vz,
+                               float2* __restrict__ rec) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rec[3 * i] = make_float2(x[i], y[i]);
+    rec[3 * i + 1] = make_float2(z[i], vx[i]);
+    rec[3 * i + 2] = make_float2(vy[i], vz[i]);
+}
+
 // members packed per group in ascending particle index (the sort is stable)
-__global__ void k_p_fill(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
-                         const float* __restrict__ z, const float* __restrict__ vx,
-                         const float* __restrict__ vy, const float* __restrict__ vz,
+__global__ void k_p_fill(int64_t n, const float2* __restrict__ rec,
                          const int32_t* __restrict__ sidx, const int32_t* __restrict__ flag,
                          const int32_t* __restrict__ rex, const int32_t* __restrict__ rstart,
                          const int32_t* __restrict__ keep, const int32_t* __restrict__ gid,
@@ -94,12 +106,13 @@ __global__ void k_p_fill(int64_t n, const float* __restrict__ x, const float* __
         return;
     }
     int64_t pos = (int64_t)goff[r] + (p - rstart[r]);
-    A.x[pos] = x[i];
-    A.y[pos] = y[i];
-    A.z[pos] = z[i];
-    A.vx[pos] = vx[i];
-    A.vy[pos] = vy[i];
-    A.vz[pos] = vz[i];
+    const float2 a = rec[3 * (int64_t)i], b = rec[3 * (int64_t)i + 1], c = rec[3 * (int64_t)i + 2];
+    A.x[pos] = a.x;
+    A.y[pos] = a.y;
+    A.z[pos] = b.x;
+    A.vx[pos] = b.y;
+    A.vy[pos] = c.x;
+    A.vz[pos] = c.y;
     A.idx[pos] = i;
     deepest[i] = gid[r];
 }
@@ -296,8 +309,9 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     // ---- arena 1: level-0 tables, records, output sort ----
     size_t bytes = 0;
     auto add = [&](size_t b) { bytes += arena_round(b); };
-    add(8 * (size_t)n); add(8 * (size_t)n);                   // label keys in / out
-    add(4 * (size_t)n); add(4 * (size_t)n);                   // index in / out
+    add(24 * (size_t)n);                                       // label keys in, out, index in;
+                                                               // then the interleaved records
+    add(4 * (size_t)n);                                        // index out
     for (int k = 0; k < 8; k++) add(4 * ((size_t)n + 1));     // flag rex rstart keep klen gid goff deepest
     for (int k = 0; k < 7; k++) add(4 * (size_t)n);           // A
     for (int k = 0; k < 9; k++) add(4 * (size_t)cap);         // records
@@ -314,9 +328,13 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     add(4 * model_floats);
     Arena* ar;
     RS_TRY(arena_reserve(AR_BASE, bytes, &ar));
-    uint64_t* lkin = take<uint64_t>(ar, n);
-    uint64_t* lkout = take<uint64_t>(ar, n);
-    int32_t* lvin = take<int32_t>(ar, n);
+    // the label sort's keys and input indices share one region, which holds
+    // the interleaved coordinates once they are consumed
+    char* lreg = take<char>(ar, 24 * (size_t)n);
+    uint64_t* lkin = reinterpret_cast<uint64_t*>(lreg);
+    uint64_t* lkout = reinterpret_cast<uint64_t*>(lreg + 8 * (size_t)n);
+    int32_t* lvin = reinterpret_cast<int32_t*>(lreg + 16 * (size_t)n);
+    float2* prec = reinterpret_cast<float2*>(lreg);
     int32_t* sidx = take<int32_t>(ar, n);
     int32_t* flag = take<int32_t>(ar, n + 1);
     int32_t* rex = take<int32_t>(ar, n + 1);
@@ -371,6 +389,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
     while (lbits < 31 && ((int64_t)1 << lbits) < n) lbits++;
     RS_TRY(sort_pairs_u64_i32(lkin, lkout, lvin, sidx, n, lbits, stemp, stb, st));
     k_p_runflag<<<gb, BT, 0, st>>>(n, lkout, flag);
+    k_p_interleave<<<gb, BT, 0, st>>>(n, x, y, z, vx, vy, vz, prec);
     RS_HIP(hipGetLastError());
     RS_TRY(scan_exclusive_i32(flag, rex, n, ctemp, ctr + 1, st));
     k_p_runstart<<<gb, BT, 0, st>>>(n, flag, rex, rstart);
@@ -392,8 +411,7 @@ static int phase_attempt(const float* x, const float* y, const float* z, const f
         *overflow = true;
         return RS_OK;
     }
-    k_p_fill<<<gb, BT, 0, st>>>(n, x, y, z, vx, vy, vz, sidx, flag, rex, rstart, keep, gid, goff,
-                                A, deepest);
+    k_p_fill<<<gb, BT, 0, st>>>(n, prec, sidx, flag, rex, rstart, keep, gid, goff, A, deepest);
     k_p_class<<<grid_for(nruns, BT, 1ll << 31), BT, 0, st>>>(nruns, rstart, keep, gid, goff, sidx,
                                                               nr, buckets, bstride, ctr + 8,
                                                               large0, ctr + 12);
