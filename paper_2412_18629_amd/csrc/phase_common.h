@@ -183,6 +183,7 @@ struct LargeWork {
     int8_t* cclass;
     unsigned long long* mpk;
     float* d2;
+    float* lrec;   // interleaved member records of the level's gather (aliases par..d2)
     LNode* nodes;
     LItem* items;
     LParam* prm;

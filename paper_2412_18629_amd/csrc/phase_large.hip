@@ -157,39 +157,54 @@ RS_DEV uint64_t morton6(const uint32_t q[6]) {
     return k;
 }
 
+// Morton keys of the level's members (node rank above them), and each
+// member's coordinates and index interleaved at its position t, 28 bytes a
+// member, so that the gather in Morton order fetches one record (one or two
+// cache lines) per member instead of seven scattered values
 __global__ void __launch_bounds__(256)
 k_lkeys(const LItem* __restrict__ items, Members in, const LParam* __restrict__ prm,
-        PhaseParams pp, uint64_t* __restrict__ keys, int32_t* __restrict__ src) {
+        PhaseParams pp, uint64_t* __restrict__ keys, int32_t* __restrict__ src,
+        float* __restrict__ rec) {
     const LItem it = items[blockIdx.x];
     const LParam P = prm[it.v];
     for (int j = threadIdx.x; j < it.len; j += 256) {
         int64_t g = it.in_start + j;
+        const float x = in.x[g], y = in.y[g], z = in.z[g];
+        const float vx = in.vx[g], vy = in.vy[g], vz = in.vz[g];
         uint32_t q[6];
-        q[0] = squash7(min_image(in.x[g] - P.cx, pp.L, pp.h) * P.sa);
-        q[1] = squash7(min_image(in.y[g] - P.cy, pp.L, pp.h) * P.sa);
-        q[2] = squash7(min_image(in.z[g] - P.cz, pp.L, pp.h) * P.sa);
-        q[3] = squash7((in.vx[g] - P.cu) * P.sc);
-        q[4] = squash7((in.vy[g] - P.cv) * P.sc);
-        q[5] = squash7((in.vz[g] - P.cw) * P.sc);
+        q[0] = squash7(min_image(x - P.cx, pp.L, pp.h) * P.sa);
+        q[1] = squash7(min_image(y - P.cy, pp.L, pp.h) * P.sa);
+        q[2] = squash7(min_image(z - P.cz, pp.L, pp.h) * P.sa);
+        q[3] = squash7((vx - P.cu) * P.sc);
+        q[4] = squash7((vy - P.cv) * P.sc);
+        q[5] = squash7((vz - P.cw) * P.sc);
         int64_t t = it.t_start + j;
         keys[t] = ((uint64_t)it.v << 42) | morton6(q);
-        src[t] = (int32_t)g;
+        src[t] = (int32_t)t;
+        float* r = rec + 7 * t;
+        r[0] = x;
+        r[1] = y;
+        r[2] = z;
+        r[3] = vx;
+        r[4] = vy;
+        r[5] = vz;
+        r[6] = __int_as_float(in.idx[g]);
     }
 }
 
 __global__ void k_lgather(int64_t m, const int32_t* __restrict__ perm,
-                          const uint64_t* __restrict__ skeys, Members in, Members out,
-                          int32_t* __restrict__ mnode) {
+                          const uint64_t* __restrict__ skeys, const float* __restrict__ rec,
+                          Members out, int32_t* __restrict__ mnode) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= m) return;
-    int32_t s = perm[t];
-    out.x[t] = in.x[s];
-    out.y[t] = in.y[s];
-    out.z[t] = in.z[s];
-    out.vx[t] = in.vx[s];
-    out.vy[t] = in.vy[s];
-    out.vz[t] = in.vz[s];
-    out.idx[t] = in.idx[s];
+    const float* r = rec + 7 * (int64_t)perm[t];
+    out.x[t] = r[0];
+    out.y[t] = r[1];
+    out.z[t] = r[2];
+    out.vx[t] = r[3];
+    out.vy[t] = r[4];
+    out.vz[t] = r[5];
+    out.idx[t] = __float_as_int(r[6]);
     mnode[t] = (int32_t)(skeys[t] >> 42);
 }
 
@@ -668,8 +683,9 @@ size_t large_work_bytes(int64_t m, int32_t min_sub) {
     auto add = [&](size_t x) { b += arena_round(x); };
     for (int k = 0; k < 2 * 7; k++) add(4 * m);                 // T, SN
     add(8 * m); add(8 * m);                                     // keys
-    for (int k = 0; k < 7; k++) add(4 * m);                     // src..cfill
-    add(8 * m); add(m); add(8 * m); add(4 * m);                 // coff, cclass, mpk, d2
+    add(4 * m); add(4 * m); add(4 * m);                         // src, perm, mnode
+    add(28 * m);                                                // par..cfill, mpk, d2 (records)
+    add(8 * m); add(m);                                         // coff, cclass
     add(sizeof(LNode) * nodes); add(sizeof(LItem) * items); add(sizeof(LParam) * nodes);
     add(8 * 18 * nodes); add(4 * 6 * nodes); add(4 * 256 * nodes);
     add(4 * tiles); add(4 * supers); add(4 * 12 * tiles); add(4 * 12 * supers);
@@ -699,14 +715,19 @@ int large_work_carve(Arena* ar, int64_t m, int32_t min_sub, LargeWork* w) {
     w->src = take<int32_t>(ar, m);
     w->perm = take<int32_t>(ar, m);
     w->mnode = take<int32_t>(ar, m);
-    w->par = take<int32_t>(ar, m);
-    w->cnt = take<int32_t>(ar, m);
-    w->cslot = take<int32_t>(ar, m);
-    w->cfill = take<int32_t>(ar, m);
+    // union-find, component and child tables and the NN distances share one
+    // region: none is live from one level's end to its next level's gather,
+    // which keeps the interleaved member records there (28 bytes a member)
+    char* reg = take<char>(ar, 28 * (size_t)m);
+    w->par = reinterpret_cast<int32_t*>(reg);
+    w->cnt = reinterpret_cast<int32_t*>(reg + 4 * (size_t)m);
+    w->cslot = reinterpret_cast<int32_t*>(reg + 8 * (size_t)m);
+    w->cfill = reinterpret_cast<int32_t*>(reg + 12 * (size_t)m);
+    w->mpk = reinterpret_cast<unsigned long long*>(reg + 16 * (size_t)m);
+    w->d2 = reinterpret_cast<float*>(reg + 24 * (size_t)m);
+    w->lrec = reinterpret_cast<float*>(reg);
     w->coff = take<int64_t>(ar, m);
     w->cclass = take<int8_t>(ar, m);
-    w->mpk = take<unsigned long long>(ar, m);
-    w->d2 = take<float>(ar, m);
     w->nodes = take<LNode>(ar, w->cap_nodes);
     w->items = take<LItem>(ar, w->cap_items);
     w->prm = take<LParam>(ar, w->cap_nodes);
@@ -889,13 +910,13 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
     k_lmom<<<ni, 256, 0, st>>>(w->items, w->nodes, in, X, Y, Z, pp, w->gacc, w->gext);
     k_lnorm<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->gacc, w->gext, X, Y, Z, pp, nr,
                                              w->prm);
-    k_lkeys<<<ni, 256, 0, st>>>(w->items, in, w->prm, pp, w->kin, w->src);
+    k_lkeys<<<ni, 256, 0, st>>>(w->items, in, w->prm, pp, w->kin, w->src, w->lrec);
     RS_HIP(hipGetLastError());
     int vbits = 1;
     while ((1 << vbits) < nv) vbits++;
     RS_TRY(sort_pairs_u64_i32(w->kin, w->kout, w->src, w->perm, M, 42 + vbits, w->sort_temp,
                               w->sort_temp_bytes, st));
-    k_lgather<<<gm, BT, 0, st>>>(M, w->perm, w->kout, in, w->T, w->mnode);
+    k_lgather<<<gm, BT, 0, st>>>(M, w->perm, w->kout, w->lrec, w->T, w->mnode);
     k_ltbox<<<tiles, 64, 0, st>>>(w->tile_node, w->nodes, w->T, w->prm, pp, w->tbox);
     k_lsbox<<<supers, 64, 0, st>>>(w->super_node, w->nodes, w->tbox, w->sbox);
     k_lcull<<<grid_for(nv, 64), 64, 0, st>>>(nv, w->nodes, w->sbox, pp, w->prm);
