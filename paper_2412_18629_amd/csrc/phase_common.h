@@ -115,9 +115,16 @@ struct TArgs {
     TreeBuf tb;
     Members T;
     PhaseParams pp;
-    float slack;
     int64_t nmem;            // members at this level
 };
+
+// Absolute slack of the box lower bounds on unwrapped positions: it covers
+// the fp32 rounding of each member's position relative to the node's
+// reference member, of the pair difference and of the image shift (at most
+// 3 units of 2^-24 L) and the rounding of the bound's own differences.  The
+// search tree stores its position boxes widened by it (rounded outward), so
+// that a bound is the plain gap to the widened box.
+__host__ __device__ inline float box_slack(float L) { return 8.0f * L * 5.9604645e-08f; }
 
 // A member's coordinate.  With O32 (fewer than 2^30 members) the byte offset
 // is formed in 32 bits, so the six loads of one member share one offset

@@ -299,37 +299,6 @@ __global__ void k_lcull(int nv, const LNode* __restrict__ nodes, const float* __
     prm[v].cull = ok ? 1 : 0;
 }
 
-// Exact lower bound of the computed d^2 between a member (w: unwrapped
-// position, u: velocity) and any member inside a box.  Position gaps lose an
-// absolute slack covering the rounding of x - x_ref, of the pair difference
-// and of the image shift (<= 3 * 2^-24 * L); velocity gaps a relative 2^-20;
-// the result a relative 1e-5 for the roundings of the bound itself and of
-// the metric.
-RS_DEV float box_lb(const float* __restrict__ b, const float w[3], const float u[3], float a,
-                    float c, float slack) {
-    float sp = 0.0f, sv = 0.0f;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        float g = fmaxf(fmaxf(b[d] - w[d], w[d] - b[6 + d]), 0.0f);
-        g = fmaxf(g - slack, 0.0f);
-        sp += g * g;
-        float h = fmaxf(fmaxf(b[3 + d] - u[d], u[d] - b[9 + d]), 0.0f) * 0.99999905f;
-        sv += h * h;
-    }
-    return (a * sp + c * sv) * 0.99999f;
-}
-
-struct LKArgs {
-    const int32_t* tile_node;
-    const LNode* nodes;
-    const LParam* prm;
-    const float* tbox;
-    const float* sbox;
-    Members T;
-    PhaseParams pp;
-    float slack;
-};
-
 // ---------------------------------------------------------------------------
 // per-node radix select over the d^2 bit patterns
 // ---------------------------------------------------------------------------
@@ -934,7 +903,7 @@ int large_level(LargeWork* w, const std::vector<ChildOut>& hn, const Members& in
         RS_TRY(tree_reserve(w, w->cap_m, w->cap_nodes, grow));
     }
     TArgs TA{w->mnode, w->tile_node, w->nodes, w->prm, w->root, w->tb, w->T, pp,
-             8.0f * pp.L * 5.9604645e-08f, M};
+             M};
     // proposer features (when requested or when a proposal is wanted)
     const bool learned = w->model != nullptr;
     if (pp.want_feat || learned) {

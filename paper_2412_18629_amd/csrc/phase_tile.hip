@@ -43,16 +43,16 @@ RS_DEV TileRec trec_load(const float* __restrict__ erec, int32_t k) {
 
 // exact lower bound of the computed d^2 between a point (w: unwrapped
 // position, u: velocity) or a box (wlo..whi, ulo..uhi) and a record's box;
-// position gaps lose an absolute slack covering the rounding of the
-// coordinates relative to the reference member, of the pair difference and
-// of the image shift; velocity gaps and the bound a relative margin
+// the record's position box is stored widened by the slack that covers the
+// rounding of the coordinates relative to the reference member, of the pair
+// difference and of the image shift; velocity gaps and the bound lose a
+// relative margin
 RS_DEV float box_box_lb(const float blo[6], const float bhi[6], const TileRec& r, float a,
-                        float c, float slack) {
+                        float c) {
     float sp = 0.0f, sv = 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        float g = fmaxf(fmaxf(r.lo[d] - bhi[d], blo[d] - r.hi[d]), 0.0f);
-        g = fmaxf(g - slack, 0.0f);
+        const float g = fmaxf(fmaxf(r.lo[d] - bhi[d], blo[d] - r.hi[d]), 0.0f);
         sp += g * g;
         float h = fmaxf(fmaxf(r.lo[3 + d] - bhi[3 + d], blo[3 + d] - r.hi[3 + d]), 0.0f) *
                   0.99999905f;
@@ -150,7 +150,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
         for (int li = 0; li < n; li++) {
             const TileRec r = trec_load(tb.erec, list[li]);
             bool need = act && r.end > mq + 1;
-            if (need && cull) need = !(box_box_lb(qpt, qpt, r, P.a, P.c, A.slack) > l2);
+            if (need && cull) need = !(box_box_lb(qpt, qpt, r, P.a, P.c) > l2);
             uint64_t mk = __ballot(need);
             if (!mk) continue;
             const int64_t mj = r.start + lane;
@@ -231,7 +231,7 @@ k_tile_link(TArgs A, int ntiles, int chunk, const float* __restrict__ d2,
                 r = trec_load(tb.erec, k);
                 leaf = r.cfirst < 0;
                 need = r.end > first_act + 1 &&
-                       (!cull || !(box_box_lb(blo, bhi, r, P.a, P.c, A.slack) > l2));
+                       (!cull || !(box_box_lb(blo, bhi, r, P.a, P.c) > l2));
             }
             const uint64_t imask = __ballot(need && !leaf);
             if (need && !leaf)

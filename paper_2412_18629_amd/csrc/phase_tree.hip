@@ -170,7 +170,8 @@ RS_DEV float wmin_nonneg(float x) {
     return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
 }
 
-// leaf boxes (wave per entry) and the leaf of every member
+// leaf boxes (wave per entry) and the leaf of every member; position
+// extents widened by the bounds' slack
 __global__ void __launch_bounds__(256)
 k_tree_leafbox(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict__ mnode,
                const LParam* __restrict__ prm, PhaseParams pp) {
@@ -191,10 +192,15 @@ k_tree_leafbox(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __restrict
         c[5] = T.vz[m];
         tb.leaf_of[m] = e;
     }
+    const float slack = box_slack(pp.L);
 #pragma unroll
     for (int d = 0; d < 6; d++) {
         float lo = wmin(ok ? c[d] : __builtin_huge_valf());
         float hi = wmax(ok ? c[d] : -__builtin_huge_valf());
+        if (d < 3 && lo <= hi) {
+            lo = nextafterf(lo - slack, -__builtin_huge_valf());
+            hi = nextafterf(hi + slack, __builtin_huge_valf());
+        }
         if (lane == 0) {
             tb.erec[16 * (int64_t)e + d] = lo;
             tb.erec[16 * (int64_t)e + 6 + d] = hi;
@@ -233,10 +239,15 @@ k_tree_leafbox_active(int32_t n_entry, TreeBuf tb, Members T, const int32_t* __r
         c[4] = T.vy[m];
         c[5] = T.vz[m];
     }
+    const float slack = box_slack(pp.L);
 #pragma unroll
     for (int d = 0; d < 6; d++) {
         float lo = wmin(ok ? c[d] : __builtin_huge_valf());
         float hi = wmax(ok ? c[d] : -__builtin_huge_valf());
+        if (d < 3 && lo <= hi) {
+            lo = nextafterf(lo - slack, -__builtin_huge_valf());
+            hi = nextafterf(hi + slack, __builtin_huge_valf());
+        }
         if (lane == 0) {
             tb.erec[16 * (int64_t)e + d] = lo;
             tb.erec[16 * (int64_t)e + 6 + d] = hi;
@@ -334,15 +345,14 @@ RS_DEV Rec rec_load(const float* __restrict__ erec, int32_t k) {
 }
 
 // exact lower bound of the computed d^2 from the query to any member of a
-// record's box (slack: absolute on unwrapped positions, covering
-// the rounding of x - x_ref, of the pair difference and of the image shift;
-// relative on velocities and on the bound itself)
-RS_DEV float rec_lb(const Rec& r, const TQuery& q, float a, float c, float slack) {
+// record's box: the position gap is to the box widened by the slack (which
+// covers the rounding of x - x_ref, of the pair difference and of the image
+// shift); velocity gaps and the bound itself lose a relative margin
+RS_DEV float rec_lb(const Rec& r, const TQuery& q, float a, float c) {
     float sp = 0.0f, sv = 0.0f;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        float g = fmaxf(fmaxf(r.lo[d] - q.wq[d], q.wq[d] - r.hi[d]), 0.0f);
-        g = fmaxf(g - slack, 0.0f);
+        const float g = fmaxf(fmaxf(r.lo[d] - q.wq[d], q.wq[d] - r.hi[d]), 0.0f);
         sp += g * g;
         float h = fmaxf(fmaxf(r.lo[3 + d] - q.uq[d], q.uq[d] - r.hi[3 + d]), 0.0f) * 0.99999905f;
         sv += h * h;
@@ -485,7 +495,7 @@ k_tree_nn(TArgs A, int ntiles, int chunk, float* __restrict__ d2out) {
                 float lb = 0.0f;
                 if (valid && k != e0) {
                     r = rec_load(tb.erec, k);
-                    lb = cull ? rec_lb(r, q, P.a, P.c, A.slack) : 0.0f;
+                    lb = cull ? rec_lb(r, q, P.a, P.c) : 0.0f;
                     need = lb < best;
                 } else {
                     r.start = r.end = 0;
