@@ -7,14 +7,15 @@
 //             monotone log-like squash per axis); node rank in the top bits
 //   sort      key/index radix sort -> members of a node are contiguous and
 //             6D-local; 64 consecutive members form a tile, 64 tiles a
-//             super-tile; each has a 6D bounding box (positions unwrapped
-//             around the node's reference member, raw velocities)
-//   NN        one wavefront per tile; candidate tiles are visited outward
-//             from the own super-tile and skipped when an exact lower bound
-//             of d^2 over the whole box cannot beat the lane's best
+//             super-tile, whose boxes decide whether a node may be culled
+//   tree      6D Morton-prefix search tree with exact boxes (phase_tree.hip)
+//   NN        per query, a depth-first search of its node's tree, bounded
+//             by the exact box lower bound (bracketed when a proposal is
+//             given, then verified and refined)
 //   select    per-node 4-pass radix select of the k-th smallest d^2
-//   link      one wavefront per tile against later tiles, skipped when the
-//             box lower bound exceeds l^2; global lock-free union-find
+//   link      one wavefront per tile: one tree walk with the tile's box,
+//             replays of the admitted leaves (phase_tile.hip); global
+//             lock-free union-find
 //   children  components of >= min_sub members (not the whole node): small
 //             ones go to the workgroup-subtree kernel, large ones to the
 //             next level
