@@ -141,20 +141,34 @@ __global__ void k_lnorm(int nv, const LNode* __restrict__ nodes,
     nr.sv2[nd.slot] = nm.sv2;
 }
 
-// squash a normalised coordinate into [0, 128): finer near the centre
+// squash a normalised coordinate into [0, 128): finer near the centre,
+// sign(u) log2(1 + 8|u|) / 5 clamped to [-1, 1].  The key only orders the
+// members for the search tree (any monotone squash gives the same results),
+// so the hardware base-2 logarithm serves.
 RS_DEV uint32_t squash7(float u) {
-    float t = copysignf(log1pf(8.0f * fabsf(u)) * 0.28853901f, u);   // 1/ln(33)
+    float t = copysignf(__log2f(1.0f + 8.0f * fabsf(u)) * 0.2f, u);
     t = fminf(fmaxf(t, -1.0f), 1.0f);
     int q = (int)((t + 1.0f) * 63.999f);
     return (uint32_t)(q < 0 ? 0 : (q > 127 ? 127 : q));
 }
 
+// the 7 bits of v moved to bit positions 0, 6, 12, ..., 36 (bit k by 5k,
+// in three shift-and-mask steps: by 20 for k >= 4, by 10 for k in {2, 3, 6},
+// by 5 for odd k)
+RS_DEV uint64_t spread7(uint32_t v) {
+    uint64_t x = v & 0x7fu;
+    x = (x | (x << 20)) & 0x000000000700000Full;
+    x = (x | (x << 10)) & 0x0000001003003003ull;
+    x = (x | (x << 5)) & 0x0000001041041041ull;
+    return x;
+}
+
+// 42-bit Morton code of six 7-bit coordinates: bit b of coordinate d at
+// position 6b + 5 - d
 RS_DEV uint64_t morton6(const uint32_t q[6]) {
     uint64_t k = 0;
 #pragma unroll
-    for (int b = 6; b >= 0; b--)
-#pragma unroll
-        for (int d = 0; d < 6; d++) k = (k << 1) | ((q[d] >> b) & 1u);
+    for (int d = 0; d < 6; d++) k |= spread7(q[d]) << (5 - d);
     return k;
 }
 
